@@ -1,0 +1,246 @@
+/*
+ * wake.h -- C ABI of the MI355X (gfx950) quasi-static plasma-response library.
+ *
+ * The library computes the hot path of the quasi-static method of
+ * Jain, Palastro, Antonsen, Mori and An, "Plasma wakefield acceleration
+ * studies using the quasi-static code WAKE" (arXiv:1411.3246):
+ *   - the plasma response to a frozen beam, marched slice by slice in
+ *     xi = c t - z over an r-xi (cylindrical) or x-xi (slab) grid
+ *     (Section II A, Eqs. (1)-(7));
+ *   - the beam current from Eq. (12) or from beam macroparticles;
+ *   - the beam advance over the long time step in the frozen fields
+ *     (Section II A, Eqs. (8)-(11); plasma first, then beam).
+ *
+ * Units are normalized: lengths k_p^-1, time omega_p^-1, momenta m_e c,
+ * potentials m_e c^2/e, fields m_e c omega_p/e, densities n_p, currents
+ * e n_p c.  Plasma and beam particles are electrons (q = -1).
+ *
+ * Conventions for every call:
+ *   - All buffers are caller-owned.  Pointers named d_* are device pointers
+ *     (HIP device memory on the current device); h_* are host pointers.
+ *     The library never allocates or frees device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is enqueued asynchronously; argument errors are reported
+ *     synchronously by the return value, device-side numeric events through
+ *     the caller's counter array (see wk_counter_index).
+ *   - A plan is host-only, immutable after creation and may be shared by
+ *     calls on different streams; it is not thread-safe to destroy while in
+ *     use.
+ *   - Layouts are structure-of-arrays.  Node arrays have n_r + 1 entries
+ *     (node j at r_j = j r_max / n_r); slice-node arrays are slice-major
+ *     [n_xi][n_r + 1] (slice k at xi_k = xi_min + k (xi_max - xi_min)/n_xi).
+ *   - "real" below means double for WK_FP64 plans and float for WK_MIXED
+ *     plans.
+ */
+#ifndef WAKE_H
+#define WAKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WK_OK = 0,
+    WK_ERR_INVALID_ARG = -1,   /* bad problem field, size or null pointer */
+    WK_ERR_UNSUPPORTED = -2,   /* valid but outside what this build handles */
+    WK_ERR_BUFFER = -3,        /* misaligned or missing buffer */
+    WK_ERR_HIP = -4,           /* a HIP runtime call failed */
+    WK_ERR_NUMERIC = -5        /* non-finite field values were produced */
+} wk_status;
+
+typedef enum { WK_CYL = 0, WK_SLAB = 1 } wk_geom;
+/* WK_FP64: every operation in double.  WK_MIXED: per-particle arithmetic in
+ * float; particle positions and momenta, deposit accumulation, the radial
+ * field solves and the xi integration stay double. */
+typedef enum { WK_FP64 = 0, WK_MIXED = 1 } wk_prec;
+
+/* One Gaussian bunch of Eq. (12): peak density (units of n_p), rms length
+ * sigma_z and centre xi_c (both in k_p^-1). */
+typedef struct {
+    double n_peak;
+    double sigma_z;
+    double xi_c;
+} wk_bunch;
+
+/* The problem statement of Section II: uniform plasma of density n0 and
+ * thermal momentum spread u_th (per component, units of m_e c); an r-xi
+ * window [0, r_max] x [xi_min, xi_max) with n_r cells and n_xi slices;
+ * ppc ring macroparticles per radial cell (even when u_th > 0: mirrored
+ * pairs); the two-bunch beam of Eq. (12) with common radial size sigma_r
+ * (n_bunch = 1 gives the single-bunch driver, n_w = 0).  With n_beam > 0 the
+ * beam is represented by macroparticles (first n_drive in bunch 0), energy
+ * gamma0 (1 + rel_spread eps), zero emittance.  d_min floors D = gamma - p_z
+ * (Eqs. (2)-(3)); floored evaluations are counted. */
+typedef struct {
+    int32_t geom;          /* wk_geom */
+    int32_t n_r;           /* radial cells, 2 .. 2048 */
+    double r_max;
+    int32_t n_xi;          /* slices, >= 1 */
+    double xi_min, xi_max;
+    int32_t ppc;           /* macroparticles per cell, 1 .. 128 */
+    double u_th;           /* >= 0 */
+    double n0;             /* plasma density (1 in normalized units) */
+    double sigma_r;
+    int32_t n_bunch;       /* 0, 1 or 2 */
+    wk_bunch bunch[2];
+    int64_t n_beam;        /* beam macroparticles (0: analytic Eq. (12) current) */
+    int64_t n_drive;       /* macroparticles of bunch 0 */
+    double gamma0, rel_spread;
+    int32_t prec;          /* wk_prec */
+    double d_min;          /* > 0 */
+} wk_problem;
+
+typedef struct wk_plan wk_plan;
+
+/* Byte sizes of every caller buffer of a plan (all multiples of 256). */
+typedef struct {
+    int64_t n_plasma;         /* plasma macroparticles in one slice = n_r * ppc */
+    int64_t n_nodes;          /* n_r + 1 */
+    size_t plasma_state;      /* one of x, y, px, py: n_plasma doubles */
+    size_t plasma_const;      /* one of d0, w: n_plasma reals */
+    size_t plasma_draws;      /* 3 doubles per particle pair */
+    size_t nion;              /* n_nodes doubles */
+    size_t beam_current;      /* n_xi * n_nodes doubles */
+    size_t fields;            /* 4 * n_xi * n_nodes reals: psi, E_z, B_theta, W */
+    size_t beam_state;        /* one of x, y, px, py, pz, xi, w, gamma_init: n_beam doubles */
+    size_t beam_tag;          /* n_beam int32 */
+    size_t beam_draws;        /* 4 doubles per beam macroparticle */
+    size_t workspace;         /* scratch for wk_plasma_response / beam calls */
+    size_t counters;          /* WK_NCOUNTERS uint64 */
+} wk_sizes;
+
+/* Plasma macroparticles of one slice: transverse Cartesian position and
+ * momentum of each ring's electron (cylindrical: ring radius |(x, y)|;
+ * slab: x, with py the conserved canonical momentum p_y, y unused), the
+ * invariant D0 = gamma0 - p_z0 of Eq. (1), the flux weight w, and the ion
+ * density n_ion on the nodes. */
+typedef struct {
+    double* d_x;
+    double* d_y;
+    double* d_px;
+    double* d_py;
+    void* d_d0;     /* real[n_plasma] */
+    void* d_w;      /* real[n_plasma] */
+    double* d_nion; /* double[n_nodes] */
+} wk_plasma_bufs;
+
+/* Beam macroparticles (lab-frame transverse position, momentum, xi, charge
+ * weight, initial gamma for gain diagnostics, bunch tag 0/1). */
+typedef struct {
+    double* d_x;
+    double* d_y;
+    double* d_px;
+    double* d_py;
+    double* d_pz;
+    double* d_xi;
+    double* d_w;
+    double* d_gamma_init;
+    int32_t* d_tag;
+} wk_beam_bufs;
+
+enum wk_counter_index {
+    WK_CNT_D_CLAMP = 0,        /* stage evaluations with D floored to d_min */
+    WK_CNT_WALL = 1,           /* plasma reflections at r_max */
+    WK_CNT_NONFINITE = 2,      /* non-finite stored field values */
+    WK_CNT_BEAM_OUT_DEPOSIT = 3,  /* beam particles outside the window (deposit) */
+    WK_CNT_BEAM_OUT_PUSH = 4,  /* beam particle-steps outside the window (push) */
+    WK_CNT_BEAM_BIN = 5,       /* beam particles that left their xi bin */
+    WK_NCOUNTERS = 8
+};
+
+const char* wk_version(void);
+const char* wk_status_string(wk_status s);
+
+/* Validate a problem and create a host-only plan (no device work, no
+ * allocation on the device).  The plan also holds the launch shape chosen
+ * for this problem size.  Returns WK_ERR_INVALID_ARG with a message in
+ * wk_last_error() when a field is out of range. */
+wk_status wk_plan_create(const wk_problem* problem, wk_plan** out);
+void wk_plan_destroy(wk_plan* plan);
+wk_status wk_plan_sizes(const wk_plan* plan, wk_sizes* out);
+/* Message of the last failed call on this thread ("" if none). */
+const char* wk_last_error(void);
+
+/* Zero a caller counter array (WK_NCOUNTERS uint64 on the device) with a
+ * kernel (safe under stream capture). */
+wk_status wk_counters_zero(uint64_t* d_counters, void* stream);
+
+/* a1, plasma: ring macroparticles at cell-uniform radii; with u_th > 0,
+ * mirrored pairs with momenta u_th * draws (d_draws: 3 standard normals per
+ * pair, pair q = cell * ppc/2 + sub-radius) and flux weights a D0/gamma0;
+ * n_ion = deposit of the initial areas (Section II A, Eq. (1) and the
+ * thermal loading it implies).  d_draws may be NULL when u_th == 0. */
+wk_status wk_init_plasma(const wk_plan* plan, const wk_plasma_bufs* plasma,
+                         const double* d_draws, void* stream);
+
+/* a1, beam: macroparticles sampling Eq. (12) from d_draws (4 standard
+ * normals per particle: x, y, xi, energy), charge weight Q_bunch / N_bunch. */
+wk_status wk_init_beam(const wk_plan* plan, const wk_beam_bufs* beam,
+                       const double* d_draws, void* stream);
+
+/* a2, analytic: J_bz = -n_b(r_j, xi_k) from Eq. (12) (fixed beam). */
+wk_status wk_beam_current_analytic(const wk_plan* plan, double* d_jb, void* stream);
+
+/* a2, macroparticles: J_bz = -sum W hat_j(r) hat_k(xi) / (V_j dxi) with
+ * v_z = c (Section II A: the total current includes the beam current).
+ * Uses the workspace for the xi binning of the beam; counts particles
+ * outside the window. */
+wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double* d_jb,
+                          void* d_workspace, uint64_t* d_counters, void* stream);
+
+/* a3-a8: one plasma response.  Marches the plasma state of `plasma` from
+ * slice 0 (unperturbed, as loaded) to slice n_xi - 1 with Heun steps,
+ * solving psi, E_z and B_theta on every slice and storing
+ * d_fields = real[4][n_xi][n_nodes] = psi, E_z, B_theta, W = E_r - B_theta.
+ * d_jb: double[n_xi][n_nodes] beam current.  The plasma state is advanced in
+ * place (load it again before the next response). */
+wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma,
+                             const double* d_jb, void* d_fields, void* d_workspace,
+                             uint64_t* d_counters, void* stream);
+
+/* Launch shape: workgroup size of the march kernel (256, 512 or 1024).  The
+ * plan picks one from the problem size; an autotuner may override it before
+ * the plan is first used. */
+wk_status wk_plan_set_threads(wk_plan* plan, int32_t threads);
+int32_t wk_plan_threads(const wk_plan* plan);
+
+/* Batched responses (a parameter scan of independent instances, any mix of
+ * sizes, all with the same geometry, precision and temperature class):
+ *   1. wk_batch_describe fills a host blob of wk_batch_desc_bytes(n) bytes
+ *      with one descriptor per instance (device pointers of its buffers and
+ *      its slice of the workspace), longest instances first;
+ *   2. the caller copies the blob to device memory;
+ *   3. wk_batch_response marches every instance in one persistent launch:
+ *      workgroups take instances from a work queue in the workspace.
+ * h_* arrays have n entries; d_workspace has wk_batch_workspace_size bytes. */
+size_t wk_batch_desc_bytes(int32_t n);
+size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans);
+wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans,
+                            const wk_plasma_bufs* h_plasma, const double* const* h_jb,
+                            void* const* h_fields, void* d_workspace, size_t workspace_bytes,
+                            uint64_t* d_counters, void* h_desc);
+wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc,
+                            void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* a9: advance the beam n_steps times by dt in the frozen fields d_fields
+ * (Eqs. (8)-(11), Boris rotation, cancellation-free d xi/dt). */
+wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields,
+                       int32_t n_steps, double dt, uint64_t* d_counters, void* stream);
+
+/* a10: charge-weighted mean gamma gain of the particles with tag == which,
+ * written to d_out[0] (deterministic two-level reduction in the
+ * workspace). */
+wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which,
+                       double* d_out, void* d_workspace, void* stream);
+/* a10: most negative on-axis E_z over slices with xi_k >= xi_from, written
+ * to d_out[0] as double. */
+wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
+                     double* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WAKE_H */

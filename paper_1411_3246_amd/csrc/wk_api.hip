@@ -1,0 +1,402 @@
+// C ABI of libwake: problem validation, plans, buffer sizes and launches.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wk_internal.h"
+
+struct wk_plan {
+    wk_problem p;
+    int32_t N;        // cells
+    int32_t N1;       // nodes
+    int64_t np;       // plasma macroparticles per slice
+    double h, dxi;
+    wk::MarchShape shape;
+    wk_sizes sizes;
+    size_t ws_fk_off, ws_beam_off;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+wk_status fail(wk_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+wk_status fail(wk_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+wk_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return WK_OK;
+    return fail(WK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t real_size(const wk_problem& p) { return p.prec == WK_FP64 ? sizeof(double) : sizeof(float); }
+
+wk::GridDesc grid_of(const wk_plan* pl)
+{
+    wk::GridDesc g;
+    g.geom = pl->p.geom;
+    g.n_r = pl->N;
+    g.n_xi = pl->p.n_xi;
+    g.r_max = pl->p.r_max;
+    g.h = pl->h;
+    g.xi_min = pl->p.xi_min;
+    g.dxi = pl->dxi;
+    return g;
+}
+
+int default_threads(int64_t np)
+{
+    if (np <= 1024) return 256;
+    if (np <= 4096) return 512;
+    return 1024;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
+
+wk_status check_plasma(const wk_plan* pl, const wk_plasma_bufs* b)
+{
+    if (!b) return fail(WK_ERR_INVALID_ARG, "plasma buffers are NULL");
+    if (!b->d_x || !b->d_px || !b->d_d0 || !b->d_w || !b->d_nion)
+        return fail(WK_ERR_BUFFER, "plasma buffer pointer is NULL");
+    const bool warm = pl->p.u_th > 0.0;
+    if (pl->p.geom == WK_CYL && warm && (!b->d_y || !b->d_py))
+        return fail(WK_ERR_BUFFER, "warm cylindrical plasma needs y and py buffers");
+    if (pl->p.geom == WK_SLAB && warm && !b->d_py)
+        return fail(WK_ERR_BUFFER, "warm slab plasma needs the py buffer");
+    if (!aligned8(b->d_x) || !aligned8(b->d_px) || !aligned8(b->d_nion))
+        return fail(WK_ERR_BUFFER, "plasma buffers must be 8-byte aligned");
+    return WK_OK;
+}
+
+wk_status check_beam(const wk_plan* pl, const wk_beam_bufs* b)
+{
+    if (!b) return fail(WK_ERR_INVALID_ARG, "beam buffers are NULL");
+    if (pl->p.n_beam <= 0) return fail(WK_ERR_INVALID_ARG, "plan has no beam macroparticles");
+    if (!b->d_x || !b->d_y || !b->d_px || !b->d_py || !b->d_pz || !b->d_xi || !b->d_w ||
+        !b->d_gamma_init || !b->d_tag)
+        return fail(WK_ERR_BUFFER, "beam buffer pointer is NULL");
+    return WK_OK;
+}
+
+wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double* jb, void* fields,
+                        void* fk, uint64_t* counters)
+{
+    wk::MarchDesc d;
+    d.geom = pl->p.geom;
+    d.warm = pl->p.u_th > 0.0 ? 1 : 0;
+    d.n_r = pl->N;
+    d.n_xi = pl->p.n_xi;
+    d.np = pl->np;
+    d.r_max = pl->p.r_max;
+    d.h = pl->h;
+    d.dxi = pl->dxi;
+    d.d_min = pl->p.d_min;
+    d.x = b->d_x;
+    d.y = b->d_y;
+    d.px = b->d_px;
+    d.py = b->d_py;
+    d.d0 = b->d_d0;
+    d.w = b->d_w;
+    d.nion = b->d_nion;
+    d.jb = jb;
+    d.fields = fields;
+    d.fk = fk;
+    d.counters = (unsigned long long*)counters;
+    d.cost = pl->np * (int64_t)pl->p.n_xi;
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wk_version(void) { return "wake-mi355x 0.1 (gfx950)"; }
+
+const char* wk_status_string(wk_status s)
+{
+    switch (s) {
+    case WK_OK: return "ok";
+    case WK_ERR_INVALID_ARG: return "invalid argument";
+    case WK_ERR_UNSUPPORTED: return "unsupported";
+    case WK_ERR_BUFFER: return "bad buffer";
+    case WK_ERR_HIP: return "HIP runtime error";
+    case WK_ERR_NUMERIC: return "non-finite values";
+    }
+    return "unknown status";
+}
+
+const char* wk_last_error(void) { return g_err.c_str(); }
+
+wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
+{
+    if (!p || !out) return fail(WK_ERR_INVALID_ARG, "NULL problem or output pointer");
+    *out = nullptr;
+    if (p->geom != WK_CYL && p->geom != WK_SLAB) return fail(WK_ERR_INVALID_ARG, "geom must be WK_CYL or WK_SLAB");
+    if (p->n_r < 2 || p->n_r > 2048) return fail(WK_ERR_INVALID_ARG, "n_r must be in [2, 2048] (got %d)", p->n_r);
+    if (p->n_xi < 1) return fail(WK_ERR_INVALID_ARG, "n_xi must be >= 1");
+    if (!(p->r_max > 0.0) || !std::isfinite(p->r_max)) return fail(WK_ERR_INVALID_ARG, "r_max must be > 0");
+    if (!(p->xi_max > p->xi_min) || !std::isfinite(p->xi_max - p->xi_min))
+        return fail(WK_ERR_INVALID_ARG, "xi_max must exceed xi_min");
+    if (p->ppc < 1 || p->ppc > 128) return fail(WK_ERR_INVALID_ARG, "ppc must be in [1, 128]");
+    if (!(p->u_th >= 0.0)) return fail(WK_ERR_INVALID_ARG, "u_th must be >= 0");
+    if (p->u_th > 0.0 && (p->ppc % 2)) return fail(WK_ERR_INVALID_ARG, "warm plasma needs an even ppc (mirrored pairs)");
+    if (!(p->n0 > 0.0)) return fail(WK_ERR_INVALID_ARG, "n0 must be > 0");
+    if (p->n_bunch < 0 || p->n_bunch > 2) return fail(WK_ERR_INVALID_ARG, "n_bunch must be 0, 1 or 2");
+    if (p->n_bunch > 0 && !(p->sigma_r > 0.0)) return fail(WK_ERR_INVALID_ARG, "sigma_r must be > 0");
+    for (int b = 0; b < p->n_bunch; ++b)
+        if (!(p->bunch[b].sigma_z > 0.0)) return fail(WK_ERR_INVALID_ARG, "bunch sigma_z must be > 0");
+    if (p->prec != WK_FP64 && p->prec != WK_MIXED) return fail(WK_ERR_INVALID_ARG, "prec must be WK_FP64 or WK_MIXED");
+    if (!(p->d_min > 0.0)) return fail(WK_ERR_INVALID_ARG, "d_min must be > 0");
+    if (p->n_beam < 0 || p->n_drive < 0 || p->n_drive > p->n_beam)
+        return fail(WK_ERR_INVALID_ARG, "need 0 <= n_drive <= n_beam");
+    if (p->n_beam > 0) {
+        if (p->n_bunch < 1) return fail(WK_ERR_INVALID_ARG, "beam macroparticles need at least one bunch");
+        if (p->n_bunch == 1 && p->n_drive != p->n_beam) return fail(WK_ERR_INVALID_ARG, "single bunch: n_drive must equal n_beam");
+        if (p->n_bunch == 2 && (p->n_drive == 0 || p->n_drive == p->n_beam))
+            return fail(WK_ERR_INVALID_ARG, "two bunches need macroparticles in both");
+        if (p->n_beam > (int64_t)0xFFFFFFF0) return fail(WK_ERR_UNSUPPORTED, "n_beam above 2^32 - 16");
+        if (!(p->gamma0 > 1.0)) return fail(WK_ERR_INVALID_ARG, "gamma0 must be > 1");
+    }
+    const int N1 = p->n_r + 1;
+    if (wk::march_lds_bytes(N1, 1024) > 160 * 1024)
+        return fail(WK_ERR_UNSUPPORTED, "n_r = %d needs more LDS than one workgroup has", p->n_r);
+
+    wk_plan* pl = new (std::nothrow) wk_plan;
+    if (!pl) return fail(WK_ERR_INVALID_ARG, "out of host memory");
+    pl->p = *p;
+    pl->N = p->n_r;
+    pl->N1 = N1;
+    pl->np = (int64_t)p->n_r * p->ppc;
+    pl->h = p->r_max / p->n_r;
+    pl->dxi = (p->xi_max - p->xi_min) / p->n_xi;
+    pl->shape.threads = default_threads(pl->np);
+    pl->shape.tile = 4;
+    const size_t rs = real_size(*p);
+    wk_sizes& s = pl->sizes;
+    s.n_plasma = pl->np;
+    s.n_nodes = N1;
+    s.plasma_state = a256(sizeof(double) * pl->np);
+    s.plasma_const = a256(rs * pl->np);
+    s.plasma_draws = a256(sizeof(double) * 3 * (pl->np / 2 + 1));
+    s.nion = a256(sizeof(double) * N1);
+    s.beam_current = a256(sizeof(double) * (size_t)p->n_xi * N1);
+    s.fields = a256(rs * 4 * (size_t)p->n_xi * N1);
+    const int64_t nb = p->n_beam > 0 ? p->n_beam : 1;
+    s.beam_state = a256(sizeof(double) * nb);
+    s.beam_tag = a256(sizeof(int32_t) * nb);
+    s.beam_draws = a256(sizeof(double) * 4 * nb);
+    pl->ws_fk_off = 0;
+    pl->ws_beam_off = a256(rs * 4 * pl->np);
+    s.workspace = pl->ws_beam_off + a256(wk::beam_ws_bytes(p->n_xi, p->n_beam));
+    s.counters = a256(sizeof(uint64_t) * WK_NCOUNTERS);
+    *out = pl;
+    g_err.clear();
+    return WK_OK;
+}
+
+void wk_plan_destroy(wk_plan* plan) { delete plan; }
+
+wk_status wk_plan_sizes(const wk_plan* plan, wk_sizes* out)
+{
+    if (!plan || !out) return fail(WK_ERR_INVALID_ARG, "NULL plan or output");
+    *out = plan->sizes;
+    return WK_OK;
+}
+
+wk_status wk_plan_set_threads(wk_plan* plan, int32_t threads)
+{
+    if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");
+    if (threads != 256 && threads != 512 && threads != 1024)
+        return fail(WK_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
+    plan->shape.threads = threads;
+    return WK_OK;
+}
+
+int32_t wk_plan_threads(const wk_plan* plan) { return plan ? plan->shape.threads : 0; }
+
+wk_status wk_counters_zero(uint64_t* d_counters, void* stream)
+{
+    if (!d_counters) return fail(WK_ERR_INVALID_ARG, "NULL counters");
+    return hip_status(wk::launch_zero_u64((unsigned long long*)d_counters, WK_NCOUNTERS, (hipStream_t)stream),
+                      "zero counters");
+}
+
+wk_status wk_init_plasma(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_draws, void* stream)
+{
+    if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
+    if (plan->p.u_th > 0.0 && !d_draws) return fail(WK_ERR_INVALID_ARG, "warm plasma needs draws");
+    return hip_status(wk::launch_init_plasma(grid_of(plan), plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec,
+                                             *plasma, d_draws, (hipStream_t)stream),
+                      "init plasma");
+}
+
+wk_status wk_init_beam(const wk_plan* plan, const wk_beam_bufs* beam, const double* d_draws, void* stream)
+{
+    if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");
+    wk_status st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    if (!d_draws) return fail(WK_ERR_INVALID_ARG, "beam loader needs draws");
+    return hip_status(wk::launch_init_beam(grid_of(plan), plan->p, *beam, d_draws, (hipStream_t)stream), "init beam");
+}
+
+wk_status wk_beam_current_analytic(const wk_plan* plan, double* d_jb, void* stream)
+{
+    if (!plan || !d_jb) return fail(WK_ERR_INVALID_ARG, "NULL plan or jb");
+    return hip_status(wk::launch_beam_current_analytic(grid_of(plan), plan->p, d_jb, (hipStream_t)stream),
+                      "analytic beam current");
+}
+
+wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double* d_jb, void* d_workspace,
+                          uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_jb || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    wk_status st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    return hip_status(wk::launch_beam_current(grid_of(plan), plan->p.n_beam, *beam, d_jb,
+                                              (char*)d_workspace + plan->ws_beam_off,
+                                              (unsigned long long*)d_counters, (hipStream_t)stream),
+                      "beam current");
+}
+
+wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb, void* d_fields,
+                             void* d_workspace, uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
+    const wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, (char*)d_workspace + plan->ws_fk_off, d_counters);
+    return hip_status(wk::launch_march(d, plan->p.prec, plan->shape, (hipStream_t)stream), "plasma response");
+}
+
+size_t wk_batch_desc_bytes(int32_t n) { return n > 0 ? a256(sizeof(wk::MarchDesc) * (size_t)n) : 0; }
+
+size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans)
+{
+    if (n <= 0 || !h_plans) return 0;
+    size_t s = 256;  // work-queue counter
+    for (int i = 0; i < n; ++i) {
+        if (!h_plans[i]) return 0;
+        s += a256(real_size(h_plans[i]->p) * 4 * h_plans[i]->np);
+    }
+    return s;
+}
+
+wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_plasma_bufs* h_plasma,
+                            const double* const* h_jb, void* const* h_fields, void* d_workspace,
+                            size_t workspace_bytes, uint64_t* d_counters, void* h_desc)
+{
+    if (n <= 0 || !h_plans || !h_plasma || !h_jb || !h_fields || !d_workspace || !d_counters || !h_desc)
+        return fail(WK_ERR_INVALID_ARG, "NULL argument or n <= 0");
+    const size_t need = wk_batch_workspace_size(n, h_plans);
+    if (need == 0) return fail(WK_ERR_INVALID_ARG, "NULL plan in batch");
+    if (workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace needs %zu bytes", need);
+    const wk_plan* p0 = h_plans[0];
+    std::vector<wk::MarchDesc> descs((size_t)n);
+    char* ws = (char*)d_workspace + 256;
+    for (int i = 0; i < n; ++i) {
+        const wk_plan* pl = h_plans[i];
+        if (pl->p.prec != p0->p.prec || pl->p.geom != p0->p.geom)
+            return fail(WK_ERR_UNSUPPORTED, "batch instances must share geometry and precision");
+        wk_status st = check_plasma(pl, &h_plasma[i]);
+        if (st != WK_OK) return st;
+        if (!h_jb[i] || !h_fields[i]) return fail(WK_ERR_INVALID_ARG, "NULL jb or fields for instance %d", i);
+        descs[i] = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], ws, d_counters);
+        ws += a256(real_size(pl->p) * 4 * pl->np);
+    }
+    // cold instances run on the warm path when the batch mixes both
+    bool any_warm = false;
+    for (auto& d : descs) any_warm |= d.warm != 0;
+    for (auto& d : descs) d.warm = any_warm ? 1 : 0;
+    // longest first
+    std::stable_sort(descs.begin(), descs.end(),
+                     [](const wk::MarchDesc& a, const wk::MarchDesc& b) { return a.cost > b.cost; });
+    std::memcpy(h_desc, descs.data(), sizeof(wk::MarchDesc) * (size_t)n);
+    return WK_OK;
+}
+
+wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc, void* d_workspace,
+                            size_t workspace_bytes, void* stream)
+{
+    if (n <= 0 || !h_plans || !d_desc || !d_workspace) return fail(WK_ERR_INVALID_ARG, "NULL argument or n <= 0");
+    const size_t need = wk_batch_workspace_size(n, h_plans);
+    if (need == 0 || workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace too small");
+    int max_nodes = 0, threads = 256;
+    bool warm = false;
+    for (int i = 0; i < n; ++i) {
+        max_nodes = std::max(max_nodes, h_plans[i]->N1);
+        threads = std::max(threads, h_plans[i]->shape.threads);
+        warm |= h_plans[i]->p.u_th > 0.0;
+    }
+    const size_t lds = wk::march_lds_bytes(max_nodes, threads);
+    int per_cu = (int)std::min<size_t>(2, (160 * 1024) / std::max<size_t>(lds, 1));
+    if (threads > 1024 / per_cu) per_cu = std::max(1, 2048 / threads / 2);
+    if (per_cu < 1) per_cu = 1;
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    const int grid = std::min(n, cus * per_cu);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned int* next = (unsigned int*)d_workspace;
+    hipError_t e = wk::launch_zero_u32(next, 1, s);
+    if (e != hipSuccess) return hip_status(e, "batch queue");
+    wk::MarchShape shape{threads, 4};
+    return hip_status(wk::launch_march_batch((const wk::MarchDesc*)d_desc, n, max_nodes, h_plans[0]->p.geom,
+                                             warm ? 1 : 0, h_plans[0]->p.prec, shape, grid, next, s),
+                      "batch response");
+}
+
+wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields, int32_t n_steps,
+                       double dt, uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_fields || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (n_steps < 0 || !std::isfinite(dt)) return fail(WK_ERR_INVALID_ARG, "bad n_steps or dt");
+    wk_status st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    return hip_status(wk::launch_beam_push(grid_of(plan), plan->p.n_beam, *beam, d_fields, plan->p.prec, n_steps, dt,
+                                           (unsigned long long*)d_counters, (hipStream_t)stream),
+                      "beam push");
+}
+
+wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which, double* d_out,
+                       void* d_workspace, void* stream)
+{
+    if (!plan || !d_out || !d_workspace) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    wk_status st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    // the partial sums sit at the end of the beam binning area
+    const size_t off = plan->ws_beam_off + wk::beam_ws_bytes(plan->p.n_xi, plan->p.n_beam) - a256(sizeof(double) * 2 * 512);
+    return hip_status(wk::launch_mean_gain(plan->p.n_beam, *beam, which, d_out, (char*)d_workspace + off,
+                                           (hipStream_t)stream),
+                      "mean gain");
+}
+
+wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from, double* d_out, void* stream)
+{
+    if (!plan || !d_fields || !d_out) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    return hip_status(wk::launch_ez_peak(grid_of(plan), d_fields, plan->p.prec, xi_from, d_out, (hipStream_t)stream),
+                      "ez peak");
+}
+
+}  // extern "C"

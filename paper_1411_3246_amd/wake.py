@@ -1,0 +1,389 @@
+"""Python binding of libwake (include/wake.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the
+computation runs in the HIP kernels of libwake.so.  The binding refuses to
+run when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwake.so")
+
+WK_CYL, WK_SLAB = 0, 1
+WK_FP64, WK_MIXED = 0, 1
+COUNTER_NAMES = ["d_clamp", "wall", "nonfinite", "beam_out_deposit", "beam_out_push", "beam_bin"]
+NCOUNTERS = 8
+
+
+class WakeError(RuntimeError):
+    pass
+
+
+class WkBunch(C.Structure):
+    _fields_ = [("n_peak", C.c_double), ("sigma_z", C.c_double), ("xi_c", C.c_double)]
+
+
+class WkProblem(C.Structure):
+    _fields_ = [("geom", C.c_int32), ("n_r", C.c_int32), ("r_max", C.c_double),
+                ("n_xi", C.c_int32), ("xi_min", C.c_double), ("xi_max", C.c_double),
+                ("ppc", C.c_int32), ("u_th", C.c_double), ("n0", C.c_double),
+                ("sigma_r", C.c_double), ("n_bunch", C.c_int32), ("bunch", WkBunch * 2),
+                ("n_beam", C.c_int64), ("n_drive", C.c_int64), ("gamma0", C.c_double),
+                ("rel_spread", C.c_double), ("prec", C.c_int32), ("d_min", C.c_double)]
+
+
+class WkSizes(C.Structure):
+    _fields_ = [("n_plasma", C.c_int64), ("n_nodes", C.c_int64), ("plasma_state", C.c_size_t),
+                ("plasma_const", C.c_size_t), ("plasma_draws", C.c_size_t), ("nion", C.c_size_t),
+                ("beam_current", C.c_size_t), ("fields", C.c_size_t), ("beam_state", C.c_size_t),
+                ("beam_tag", C.c_size_t), ("beam_draws", C.c_size_t), ("workspace", C.c_size_t),
+                ("counters", C.c_size_t)]
+
+
+class WkPlasmaBufs(C.Structure):
+    _fields_ = [("d_x", C.c_void_p), ("d_y", C.c_void_p), ("d_px", C.c_void_p),
+                ("d_py", C.c_void_p), ("d_d0", C.c_void_p), ("d_w", C.c_void_p),
+                ("d_nion", C.c_void_p)]
+
+
+class WkBeamBufs(C.Structure):
+    _fields_ = [("d_x", C.c_void_p), ("d_y", C.c_void_p), ("d_px", C.c_void_p),
+                ("d_py", C.c_void_p), ("d_pz", C.c_void_p), ("d_xi", C.c_void_p),
+                ("d_w", C.c_void_p), ("d_gamma_init", C.c_void_p), ("d_tag", C.c_void_p)]
+
+
+EXPORTS = [
+    "wk_version", "wk_status_string", "wk_plan_create", "wk_plan_destroy", "wk_plan_sizes",
+    "wk_last_error", "wk_counters_zero", "wk_init_plasma", "wk_init_beam",
+    "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
+    "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
+    "wk_batch_response", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
+]
+
+_NON_STATUS = {"wk_version", "wk_status_string", "wk_last_error", "wk_plan_destroy",
+               "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size"}
+
+_lib = None
+
+
+def lib():
+    """Load libwake.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise WakeError(f"{LIB_PATH} is missing: build it with paper_1411_3246_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER(WkProblem)
+    L.wk_version.restype = C.c_char_p
+    L.wk_status_string.restype = C.c_char_p
+    L.wk_status_string.argtypes = [C.c_int]
+    L.wk_last_error.restype = C.c_char_p
+    L.wk_plan_create.argtypes = [P, C.POINTER(vp)]
+    L.wk_plan_destroy.argtypes = [vp]
+    L.wk_plan_destroy.restype = None
+    L.wk_plan_sizes.argtypes = [vp, C.POINTER(WkSizes)]
+    L.wk_plan_set_threads.argtypes = [vp, i32]
+    L.wk_plan_threads.argtypes = [vp]
+    L.wk_plan_threads.restype = i32
+    L.wk_counters_zero.argtypes = [vp, vp]
+    L.wk_init_plasma.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp]
+    L.wk_init_beam.argtypes = [vp, C.POINTER(WkBeamBufs), vp, vp]
+    L.wk_beam_current_analytic.argtypes = [vp, vp, vp]
+    L.wk_beam_current.argtypes = [vp, C.POINTER(WkBeamBufs), vp, vp, vp, vp]
+    L.wk_plasma_response.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp, vp]
+    L.wk_batch_desc_bytes.argtypes = [i32]
+    L.wk_batch_desc_bytes.restype = C.c_size_t
+    L.wk_batch_workspace_size.argtypes = [i32, C.POINTER(vp)]
+    L.wk_batch_workspace_size.restype = C.c_size_t
+    L.wk_batch_describe.argtypes = [i32, C.POINTER(vp), C.POINTER(WkPlasmaBufs), C.POINTER(vp),
+                                    C.POINTER(vp), vp, C.c_size_t, vp, vp]
+    L.wk_batch_response.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, vp]
+    L.wk_beam_push.argtypes = [vp, C.POINTER(WkBeamBufs), vp, i32, d, vp, vp]
+    L.wk_mean_gain.argtypes = [vp, C.POINTER(WkBeamBufs), i32, vp, vp, vp]
+    L.wk_ez_peak.argtypes = [vp, vp, d, vp, vp]
+    for name in EXPORTS:
+        if name not in _NON_STATUS:
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        L = lib()
+        raise WakeError(f"{what}: {L.wk_status_string(rc).decode()} ({L.wk_last_error().decode()})")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def problem_struct(p: inputs.Problem) -> WkProblem:
+    s = WkProblem()
+    s.geom = WK_CYL if p.geom == "cyl" else WK_SLAB
+    s.n_r, s.r_max, s.n_xi = p.n_r, p.r_max, p.n_xi
+    s.xi_min, s.xi_max = p.xi_min, p.xi_max
+    s.ppc, s.u_th, s.n0 = p.ppc, p.u_th, p.n0
+    s.sigma_r = p.sigma_r
+    s.n_bunch = len(p.bunches)
+    for b, bb in enumerate(p.bunches):
+        s.bunch[b].n_peak, s.bunch[b].sigma_z, s.bunch[b].xi_c = bb.n_peak, bb.sigma_z, bb.xi_c
+    s.n_beam, s.n_drive = p.n_beam, p.n_drive
+    s.gamma0, s.rel_spread = p.gamma0, p.rel_spread
+    s.prec = WK_FP64 if p.prec == "fp64" else WK_MIXED
+    s.d_min = p.d_min
+    return s
+
+
+class Plan:
+    """A validated problem and its launch shape (host-only)."""
+
+    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None):
+        self.problem = problem
+        self._s = problem_struct(problem)
+        h = C.c_void_p()
+        _check(lib().wk_plan_create(C.byref(self._s), C.byref(h)), "wk_plan_create")
+        self.handle = h
+        if threads is not None:
+            _check(lib().wk_plan_set_threads(self.handle, threads), "wk_plan_set_threads")
+        sz = WkSizes()
+        _check(lib().wk_plan_sizes(self.handle, C.byref(sz)), "wk_plan_sizes")
+        self.sizes = sz
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.wk_plan_destroy(self.handle)
+            self.handle = None
+
+    @property
+    def threads(self) -> int:
+        return lib().wk_plan_threads(self.handle)
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.problem.prec == "fp64" else torch.float32
+
+    # -- buffers (torch tensors on the current device) -------------------------
+    def alloc_plasma(self, device="cuda") -> Dict:
+        import torch
+        n = self.problem.n_plasma
+        t = {k: torch.zeros(n, dtype=torch.float64, device=device) for k in ("x", "y", "px", "py")}
+        t["d0"] = torch.zeros(n, dtype=self.real_dtype, device=device)
+        t["w"] = torch.zeros(n, dtype=self.real_dtype, device=device)
+        t["nion"] = torch.zeros(self.problem.n_r + 1, dtype=torch.float64, device=device)
+        return t
+
+    def alloc_beam(self, device="cuda") -> Dict:
+        import torch
+        n = self.problem.n_beam
+        t = {k: torch.zeros(n, dtype=torch.float64, device=device)
+             for k in ("x", "y", "px", "py", "pz", "xi", "w", "gamma_init")}
+        t["tag"] = torch.zeros(n, dtype=torch.int32, device=device)
+        return t
+
+    def alloc_fields(self, device="cuda"):
+        import torch
+        p = self.problem
+        return torch.zeros((4, p.n_xi, p.n_r + 1), dtype=self.real_dtype, device=device)
+
+    def alloc_jb(self, device="cuda"):
+        import torch
+        p = self.problem
+        return torch.zeros((p.n_xi, p.n_r + 1), dtype=torch.float64, device=device)
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.zeros(self.sizes.workspace, dtype=torch.uint8, device=device)
+
+    @staticmethod
+    def alloc_counters(device="cuda"):
+        import torch
+        return torch.zeros(NCOUNTERS, dtype=torch.int64, device=device)
+
+    @staticmethod
+    def plasma_bufs(t: Dict) -> WkPlasmaBufs:
+        b = WkPlasmaBufs()
+        b.d_x, b.d_y, b.d_px, b.d_py = _ptr(t["x"]), _ptr(t["y"]), _ptr(t["px"]), _ptr(t["py"])
+        b.d_d0, b.d_w, b.d_nion = _ptr(t["d0"]), _ptr(t["w"]), _ptr(t["nion"])
+        return b
+
+    @staticmethod
+    def beam_bufs(t: Dict) -> WkBeamBufs:
+        b = WkBeamBufs()
+        b.d_x, b.d_y, b.d_px, b.d_py = _ptr(t["x"]), _ptr(t["y"]), _ptr(t["px"]), _ptr(t["py"])
+        b.d_pz, b.d_xi, b.d_w = _ptr(t["pz"]), _ptr(t["xi"]), _ptr(t["w"])
+        b.d_gamma_init, b.d_tag = _ptr(t["gamma_init"]), _ptr(t["tag"])
+        return b
+
+    # -- calls -----------------------------------------------------------------
+    def init_plasma(self, plasma: Dict, draws=None, stream=None):
+        b = self.plasma_bufs(plasma)
+        _check(lib().wk_init_plasma(self.handle, C.byref(b), _ptr(draws), _stream(stream)),
+               "wk_init_plasma")
+
+    def init_beam(self, beam: Dict, draws, stream=None):
+        b = self.beam_bufs(beam)
+        _check(lib().wk_init_beam(self.handle, C.byref(b), _ptr(draws), _stream(stream)),
+               "wk_init_beam")
+
+    def beam_current_analytic(self, jb, stream=None):
+        _check(lib().wk_beam_current_analytic(self.handle, _ptr(jb), _stream(stream)),
+               "wk_beam_current_analytic")
+
+    def beam_current(self, beam: Dict, jb, workspace, counters, stream=None):
+        b = self.beam_bufs(beam)
+        _check(lib().wk_beam_current(self.handle, C.byref(b), _ptr(jb), _ptr(workspace),
+                                     _ptr(counters), _stream(stream)), "wk_beam_current")
+
+    def plasma_response(self, plasma: Dict, jb, fields, workspace, counters, stream=None):
+        b = self.plasma_bufs(plasma)
+        _check(lib().wk_plasma_response(self.handle, C.byref(b), _ptr(jb), _ptr(fields),
+                                        _ptr(workspace), _ptr(counters), _stream(stream)),
+               "wk_plasma_response")
+
+    def beam_push(self, beam: Dict, fields, n_steps: int, dt: float, counters, stream=None):
+        b = self.beam_bufs(beam)
+        _check(lib().wk_beam_push(self.handle, C.byref(b), _ptr(fields), n_steps, dt,
+                                  _ptr(counters), _stream(stream)), "wk_beam_push")
+
+    def mean_gain(self, beam: Dict, which: int, out, workspace, stream=None):
+        b = self.beam_bufs(beam)
+        _check(lib().wk_mean_gain(self.handle, C.byref(b), which, _ptr(out), _ptr(workspace),
+                                  _stream(stream)), "wk_mean_gain")
+
+    def ez_peak(self, fields, xi_from: float, out, stream=None):
+        _check(lib().wk_ez_peak(self.handle, _ptr(fields), xi_from, _ptr(out), _stream(stream)),
+               "wk_ez_peak")
+
+
+def zero_counters(counters, stream=None):
+    _check(lib().wk_counters_zero(_ptr(counters), _stream(stream)), "wk_counters_zero")
+
+
+def counters_dict(counters) -> Dict[str, int]:
+    v = counters.cpu().numpy()
+    return {k: int(v[i]) for i, k in enumerate(COUNTER_NAMES)}
+
+
+# ---------------------------------------------------------------------------
+# Batched responses
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Independent plasma responses of many plans in one persistent launch."""
+
+    def __init__(self, plans: Sequence[Plan], device="cuda"):
+        import torch
+        self.plans = list(plans)
+        n = len(self.plans)
+        self._handles = (C.c_void_p * n)(*[p.handle for p in self.plans])
+        self.ws_bytes = lib().wk_batch_workspace_size(n, self._handles)
+        if self.ws_bytes == 0:
+            raise WakeError("wk_batch_workspace_size failed")
+        self.workspace = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.desc_bytes = lib().wk_batch_desc_bytes(n)
+        self.desc = torch.zeros(self.desc_bytes, dtype=torch.uint8, device=device)
+        self._described = False
+
+    def describe(self, plasmas: Sequence[Dict], jbs, fields, counters):
+        import torch
+        n = len(self.plans)
+        pb = (WkPlasmaBufs * n)(*[Plan.plasma_bufs(t) for t in plasmas])
+        jbp = (C.c_void_p * n)(*[_ptr(j) for j in jbs])
+        fp = (C.c_void_p * n)(*[_ptr(f) for f in fields])
+        host = (C.c_uint8 * self.desc_bytes)()
+        _check(lib().wk_batch_describe(n, self._handles, pb, jbp, fp, _ptr(self.workspace),
+                                       self.ws_bytes, _ptr(counters), C.cast(host, C.c_void_p)),
+               "wk_batch_describe")
+        blob = torch.frombuffer(bytearray(host), dtype=torch.uint8)
+        self.desc.copy_(blob)
+        self._described = True
+
+    def response(self, stream=None):
+        if not self._described:
+            raise WakeError("Batch.describe must be called first")
+        _check(lib().wk_batch_response(len(self.plans), self._handles, _ptr(self.desc),
+                                       _ptr(self.workspace), self.ws_bytes, _stream(stream)),
+               "wk_batch_response")
+
+
+# ---------------------------------------------------------------------------
+# Convenience: the quasi-static cycle on one plan
+# ---------------------------------------------------------------------------
+
+class Simulation:
+    """Buffers and calls of one problem: plasma response for the frozen beam,
+    then the beam advanced over dt (Section II A of the WAKE paper)."""
+
+    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None, device="cuda"):
+        import torch
+        self.problem = problem
+        self.plan = Plan(problem, threads)
+        self.device = device
+        self.plasma = self.plan.alloc_plasma(device)
+        self.fields = self.plan.alloc_fields(device)
+        self.jb = self.plan.alloc_jb(device)
+        self.workspace = self.plan.alloc_workspace(device)
+        self.counters = self.plan.alloc_counters(device)
+        self.out = torch.zeros(4, dtype=torch.float64, device=device)
+        pd = inputs.plasma_draws(problem)
+        self.plasma_draws = None if pd is None else torch.from_numpy(pd).to(device)
+        self.beam = None
+        if problem.n_beam > 0:
+            self.beam = self.plan.alloc_beam(device)
+            self.beam_draws = torch.from_numpy(inputs.beam_draws(problem)).to(device)
+        zero_counters(self.counters)
+
+    def load_beam(self):
+        if self.beam is not None:
+            self.plan.init_beam(self.beam, self.beam_draws)
+
+    def beam_current(self):
+        if self.beam is None:
+            self.plan.beam_current_analytic(self.jb)
+        else:
+            self.plan.beam_current(self.beam, self.jb, self.workspace, self.counters)
+
+    def response(self):
+        """Load the plasma ahead of the beam and march it through the window."""
+        self.plan.init_plasma(self.plasma, self.plasma_draws)
+        self.plan.plasma_response(self.plasma, self.jb, self.fields, self.workspace, self.counters)
+
+    def push(self, n_steps: int = 1, dt: Optional[float] = None):
+        self.plan.beam_push(self.beam, self.fields, n_steps, self.problem.dt if dt is None else dt,
+                            self.counters)
+
+    def step(self):
+        """One beam step: beam current -> plasma response -> beam push."""
+        self.beam_current()
+        self.response()
+        if self.beam is not None:
+            self.push(1)
+
+    def witness_gain(self) -> float:
+        self.plan.mean_gain(self.beam, 1, self.out[0:1], self.workspace)
+        return float(self.out[0].item())
+
+    def ez_peak(self, xi_from: float) -> float:
+        self.plan.ez_peak(self.fields, xi_from, self.out[1:2])
+        return float(self.out[1].item())
+
+    def counters_dict(self):
+        return counters_dict(self.counters)

@@ -1,0 +1,270 @@
+"""GPU (HIP, gfx950) vs FP64 oracle, through the C ABI.
+
+Tolerances:
+  * FP64 plans: max|gpu - oracle| / max|oracle| <= 1e-10 per field (and for
+    the particle state), where the oracle's own sensitivity to 1-ulp
+    perturbations stays below 1e-12; in the trajectory-crossing blowout the
+    bound is ten times that sensitivity envelope.
+  * Mixed plans: ||dE_z||_2 / ||E_z||_2 <= 1e-3; the other fields are
+    reported with their own bounds.
+"""
+import numpy as np
+import pytest
+
+from paper_1411_3246_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1411_3246_amd import wake
+    wake.lib()
+    return wake
+
+
+def _np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+def _l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def gpu_response(W, p, jb=None, threads=None):
+    import torch
+    sim = W.Simulation(p, threads=threads)
+    if jb is None:
+        sim.beam_current()
+    else:
+        sim.jb.copy_(torch.from_numpy(np.ascontiguousarray(jb)))
+    sim.response()
+    torch.cuda.synchronize()
+    return sim
+
+
+def oracle_response(O, p, jb=None):
+    return O.response(p, inputs.plasma_draws(p), jb=jb)
+
+
+def _state(sim):
+    return {k: _np(sim.plasma[k]) for k in ("x", "y", "px", "py")}
+
+
+def _check_fp64(O, W, p, tol=1e-10, threads=None):
+    print(f"case {p.name} {p.geom} {p.n_r}x{p.n_xi} ppc={p.ppc} u_th={p.u_th} threads={threads}",
+          flush=True)
+    ref = oracle_response(O, p)
+    sim = gpu_response(W, p, jb=ref["jb"], threads=threads)
+    f = _np(sim.fields)
+    for i, name in enumerate(("psi", "E_z", "B_theta", "W")):
+        e = _rel(f[i], ref["fields"][i])
+        assert e <= tol, (name, e)
+    st = _state(sim)
+    for k in ("x", "px", "y", "py"):
+        if np.max(np.abs(ref["state"][k])) > 0:
+            assert _rel(st[k], ref["state"][k]) <= tol, k
+    c = sim.counters_dict()
+    assert c["d_clamp"] == int(ref["counters"][0])
+    assert c["wall"] == int(ref["counters"][1])
+    assert c["nonfinite"] == 0
+    return sim, ref
+
+
+def test_library_loads_and_validates(W):
+    with pytest.raises(W.WakeError):
+        W.Plan(inputs.weak_single_bunch(ppc=0))
+
+
+def test_weak_bunch_fp64_matches_oracle(O, W):
+    """Cold plasma, fixed single bunch, 128 x 512, FP64: <= 1e-10."""
+    _check_fp64(O, W, inputs.weak_single_bunch())
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_fp64_ragged_tiles(O, W, threads):
+    """Particle counts that leave ragged tiles for every workgroup size."""
+    p = inputs.weak_single_bunch(n_r=37, n_xi=96, ppc=3, n_b0=0.5)
+    _check_fp64(O, W, p, threads=threads)
+
+
+def test_fp64_minimal_grid(O, W):
+    p = inputs.weak_single_bunch(n_r=2, n_xi=5, ppc=1, r_max=1.0, n_b0=0.3)
+    _check_fp64(O, W, p)
+
+
+def test_fp64_single_slice(O, W):
+    p = inputs.weak_single_bunch(n_xi=1)
+    _check_fp64(O, W, p)
+
+
+def test_fp64_warm_moderate(O, W):
+    """Warm plasma (Cartesian ring electrons), moderate two-bunch driver."""
+    p = inputs.facet_two_bunch(n_r=96, n_xi=600, ppc=8, u_th=0.02, n_d=1.0, n_beam=0,
+                               prec="fp64")
+    _check_fp64(O, W, p, tol=1e-9)
+
+
+def test_fp64_slab(O, W):
+    p = inputs.weak_single_bunch(geom="slab", r_max=8.0, n_r=128, n_xi=256, n_b0=0.3)
+    _check_fp64(O, W, p)
+    q = inputs.facet_two_bunch(n_r=64, n_xi=300, ppc=4, u_th=0.02, n_d=1.0, n_beam=0,
+                               prec="fp64", geom="slab", r_max=8.0)
+    _check_fp64(O, W, q, tol=1e-9)
+
+
+def test_fp64_wall_reflections(O, W):
+    """Warm plasma at a narrow wall: reflections counted as in the oracle."""
+    p = inputs.facet_two_bunch(n_r=32, n_xi=400, ppc=4, u_th=0.05, n_d=0.5, r_max=1.5,
+                               n_beam=0, prec="fp64")
+    sim, ref = _check_fp64(O, W, p, tol=1e-9)
+    assert int(ref["counters"][1]) > 0
+
+
+def _envelope(O, p):
+    """Oracle sensitivity: fields after a 1-ulp change of the initial radii."""
+    st = O.load_plasma(p, inputs.plasma_draws(p))
+    jb = O.beam_current_analytic(p)
+    f0, _, _ = O.march(p, {k: v.copy() for k, v in st.items()}, jb)
+    st["x"] = np.nextafter(st["x"], np.inf)
+    f1, _, _ = O.march(p, st, jb)
+    return f0, np.abs(f1 - f0)
+
+
+def test_fp64_blowout_within_sensitivity_envelope(O, W):
+    """Blowout with trajectory crossing: |gpu - oracle| <= 10 x the oracle's
+    own 1-ulp sensitivity (plus 1e-10 of the field scale), slice by slice."""
+    p = inputs.facet_two_bunch(n_r=128, n_xi=1024, ppc=8, u_th=0.02, n_beam=0, prec="fp64")
+    f_ref, env = _envelope(O, p)
+    sim = gpu_response(W, p)
+    f = _np(sim.fields)
+    for i in range(4):
+        scale = np.max(np.abs(f_ref[i]))
+        env_k = np.max(env[i], axis=1)            # per slice
+        env_k = np.maximum.accumulate(env_k)
+        err_k = np.max(np.abs(f[i] - f_ref[i]), axis=1)
+        assert np.all(err_k <= 10 * env_k + 1e-10 * scale), i
+    # ahead of trajectory crossing the strict bound holds
+    k0 = int(2.0 / p.dxi)
+    assert _rel(f[1, :k0], f_ref[1, :k0]) <= 1e-10
+
+
+def test_mixed_blowout_ez_within_1e3(O, W):
+    """FP32 bulk / FP64 solve: ||dE_z|| / ||E_z|| <= 1e-3 on the blowout case."""
+    p = inputs.facet_two_bunch(n_r=256, n_xi=2048, ppc=16, u_th=0.02, n_beam=0, prec="mixed")
+    ref = oracle_response(O, p.replace(prec="fp64"))
+    sim = gpu_response(W, p)
+    f = _np(sim.fields)
+    e = [_l2(f[i], ref["fields"][i]) for i in range(4)]
+    print("mixed L2 errors psi, E_z, B, W:", e, flush=True)
+    assert e[1] <= 1e-3
+    assert e[0] <= 1e-3 and e[3] <= 1e-2 and e[2] <= 1e-2
+
+
+def test_beam_current_and_push_fp64(O, W):
+    import torch
+    p = inputs.facet_two_bunch(n_r=64, n_xi=256, ppc=4, u_th=0.0, n_beam=5000, n_steps=3,
+                               prec="fp64")
+    sim = W.Simulation(p)
+    sim.load_beam()
+    ob = O.load_beam(p, inputs.beam_draws(p))
+    for k in ("x", "y", "xi", "pz", "w"):
+        assert _rel(_np(sim.beam[k]), ob[k]) <= 1e-15, k
+    sim.beam_current()
+    torch.cuda.synchronize()
+    jb_ref, nout = O.beam_current_macro(p, ob)
+    assert _rel(_np(sim.jb), jb_ref) <= 1e-12
+    sim.response()
+    torch.cuda.synchronize()
+    st = O.load_plasma(p, None)
+    fields, _, _ = O.march(p, st, jb_ref)
+    assert _rel(_np(sim.fields), fields) <= 1e-10
+    sim.push(3, p.dt)
+    torch.cuda.synchronize()
+    O.beam_push(p, ob, fields, 3, p.dt)
+    for k in ("x", "y", "px", "py", "pz", "xi"):
+        assert np.max(np.abs(_np(sim.beam[k]) - ob[k])) <= 1e-9 * max(1.0, np.max(np.abs(ob[k]))), k
+    g0 = O.beam_gamma(O.load_beam(p, inputs.beam_draws(p)))
+    gain_ref = O.mean_gain(ob, g0, 1)
+    assert sim.witness_gain() == pytest.approx(gain_ref, rel=1e-9, abs=1e-12)
+    assert sim.ez_peak(3.0) == pytest.approx(O.ez_peak(p, fields, 3.0), rel=1e-10)
+
+
+def test_cycle_mixed_witness_gain(O, W):
+    """Three quasi-static cycles (current -> response -> push) in mixed
+    precision vs the FP64 oracle: witness gain within 1e-3."""
+    import torch
+    p = inputs.facet_two_bunch(n_r=128, n_xi=1024, ppc=8, u_th=0.02, n_beam=20000, n_steps=3,
+                               prec="mixed")
+    sim = W.Simulation(p)
+    sim.load_beam()
+    for _ in range(p.n_steps):
+        sim.step()
+    torch.cuda.synchronize()
+    ref = O.cycle(p.replace(prec="fp64"), inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
+    g = sim.witness_gain()
+    assert g == pytest.approx(ref["witness_gain"], rel=1e-3)
+    assert sim.counters_dict()["nonfinite"] == 0
+
+
+def test_batch_matches_standalone(O, W):
+    """Uneven instances in one persistent launch == each run alone (FP64)."""
+    import torch
+    base = dict(n_beam=0, prec="fp64", u_th=0.02)
+    probs = [inputs.facet_two_bunch(n_r=nr, n_xi=nx, ppc=ppc, sep=sep, **base)
+             for (nr, nx, ppc, sep) in ((32, 200, 8, 3.5), (64, 333, 4, 4.0), (48, 129, 6, 5.0),
+                                        (16, 400, 2, 3.0), (64, 64, 10, 6.0))]
+    plans = [W.Plan(q) for q in probs]
+    plasmas, jbs, fields = [], [], []
+    counters = W.Plan.alloc_counters()
+    W.zero_counters(counters)
+    for q, pl in zip(probs, plans):
+        t = pl.alloc_plasma()
+        d = inputs.plasma_draws(q)
+        pl.init_plasma(t, torch.from_numpy(d).cuda())
+        jb = pl.alloc_jb()
+        pl.beam_current_analytic(jb)
+        plasmas.append(t)
+        jbs.append(jb)
+        fields.append(pl.alloc_fields())
+    batch = W.Batch(plans)
+    batch.describe(plasmas, jbs, fields, counters)
+    batch.response()
+    torch.cuda.synchronize()
+    for q, f in zip(probs, fields):
+        ref = oracle_response(O, q)
+        assert _rel(_np(f), ref["fields"]) <= 1e-9, q.name
+
+
+def test_full_size_blowout_first_response_mixed(O, W):
+    """The headline workload's first plasma response (512 x 4096, 16 ppc,
+    1e6-particle beam current) in mixed precision: E_z within 1e-3."""
+    import torch
+    p = inputs.blowout_response()
+    sim = W.Simulation(p)
+    sim.load_beam()
+    sim.beam_current()
+    sim.response()
+    torch.cuda.synchronize()
+    ob = O.load_beam(p, inputs.beam_draws(p))
+    jb_ref, _ = O.beam_current_macro(p, ob)
+    assert _rel(_np(sim.jb), jb_ref) <= 1e-12
+    st = O.load_plasma(p, inputs.plasma_draws(p))
+    fields, cnt, _ = O.march(p, st, jb_ref)
+    f = _np(sim.fields)
+    e = _l2(f[1], fields[1])
+    print("full-size mixed L2 error E_z:", e, flush=True)
+    assert e <= 1e-3
+    assert sim.counters_dict()["nonfinite"] == 0
