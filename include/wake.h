@@ -148,6 +148,7 @@ enum wk_counter_index {
     WK_CNT_BEAM_OUT_DEPOSIT = 3,  /* beam particles outside the window (deposit) */
     WK_CNT_BEAM_OUT_PUSH = 4,  /* beam particle-steps outside the window (push) */
     WK_CNT_BEAM_BIN = 5,       /* beam particles that left their xi bin */
+    WK_CNT_PIPELINE_ABORT = 6, /* nonzero: a pipelined cycle gave up waiting (results invalid) */
     WK_NCOUNTERS = 8
 };
 
@@ -224,6 +225,28 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans,
                             uint64_t* d_counters, void* h_desc);
 wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc,
                             void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* The quasi-static cycle, n_steps times: beam current from the macroparticles
+ * -> plasma response -> beam advance by dt (Section II A: the plasma responds
+ * to the frozen beam, then the beam is advanced in t).  The responses of
+ * successive steps run concurrently on separate workgroups: response n
+ * marches slice k once response n-1 has stored the slices up to k + 3, and
+ * advances the beam particles of each xi bin just before it deposits them.
+ * The result equals n_steps sequential calls of wk_beam_current,
+ * wk_plasma_response (from the same loaded plasma) and wk_beam_push(1 step)
+ * up to the summation order of the deposits.
+ *   plasma:   loaded by wk_init_plasma; read only (each response starts from it)
+ *   d_ring:   2 * sizes.fields bytes; the fields of response n are in slot
+ *             n % 2, so the last response is in slot (n_steps - 1) % 2
+ *   workspace: wk_cycle_workspace_size(plan, n_steps) bytes.
+ * Requires n_r <= 880 (LDS).  Counter WK_CNT_PIPELINE_ABORT is set if a
+ * workgroup waited too long for its predecessor (then the results are
+ * invalid); WK_CNT_BEAM_BIN counts particles whose xi moved by more than a
+ * slice during the run. */
+size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps);
+wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_beam_bufs* beam,
+                   int32_t n_steps, double dt, void* d_ring, void* d_workspace,
+                   size_t workspace_bytes, uint64_t* d_counters, void* stream);
 
 /* a9: advance the beam n_steps times by dt in the frozen fields d_fields
  * (Eqs. (8)-(11), Boris rotation, cancellation-free d xi/dt). */

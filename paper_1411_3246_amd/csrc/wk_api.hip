@@ -62,7 +62,7 @@ wk::GridDesc grid_of(const wk_plan* pl)
 
 int default_threads(int64_t np)
 {
-    if (np <= 1024) return 256;
+    if (np <= 2048) return 256;
     if (np <= 4096) return 512;
     return 1024;
 }
@@ -95,7 +95,7 @@ wk_status check_beam(const wk_plan* pl, const wk_beam_bufs* b)
 }
 
 wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double* jb, void* fields,
-                        void* fk, uint64_t* counters)
+                        uint64_t* counters)
 {
     wk::MarchDesc d;
     d.geom = pl->p.geom;
@@ -116,7 +116,6 @@ wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double
     d.nion = b->d_nion;
     d.jb = jb;
     d.fields = fields;
-    d.fk = fk;
     d.counters = (unsigned long long*)counters;
     d.cost = pl->np * (int64_t)pl->p.n_xi;
     return d;
@@ -202,7 +201,7 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
     s.beam_tag = a256(sizeof(int32_t) * nb);
     s.beam_draws = a256(sizeof(double) * 4 * nb);
     pl->ws_fk_off = 0;
-    pl->ws_beam_off = a256(rs * 4 * pl->np);
+    pl->ws_beam_off = 0;
     s.workspace = pl->ws_beam_off + a256(wk::beam_ws_bytes(p->n_xi, p->n_beam));
     s.counters = a256(sizeof(uint64_t) * WK_NCOUNTERS);
     *out = pl;
@@ -282,7 +281,7 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
     wk_status st = check_plasma(plan, plasma);
     if (st != WK_OK) return st;
-    const wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, (char*)d_workspace + plan->ws_fk_off, d_counters);
+    const wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, d_counters);
     return hip_status(wk::launch_march(d, plan->p.prec, plan->shape, (hipStream_t)stream), "plasma response");
 }
 
@@ -291,12 +290,9 @@ size_t wk_batch_desc_bytes(int32_t n) { return n > 0 ? a256(sizeof(wk::MarchDesc
 size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans)
 {
     if (n <= 0 || !h_plans) return 0;
-    size_t s = 256;  // work-queue counter
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (!h_plans[i]) return 0;
-        s += a256(real_size(h_plans[i]->p) * 4 * h_plans[i]->np);
-    }
-    return s;
+    return 256;  // work-queue counter
 }
 
 wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_plasma_bufs* h_plasma,
@@ -310,7 +306,6 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_p
     if (workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace needs %zu bytes", need);
     const wk_plan* p0 = h_plans[0];
     std::vector<wk::MarchDesc> descs((size_t)n);
-    char* ws = (char*)d_workspace + 256;
     for (int i = 0; i < n; ++i) {
         const wk_plan* pl = h_plans[i];
         if (pl->p.prec != p0->p.prec || pl->p.geom != p0->p.geom)
@@ -318,8 +313,7 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_p
         wk_status st = check_plasma(pl, &h_plasma[i]);
         if (st != WK_OK) return st;
         if (!h_jb[i] || !h_fields[i]) return fail(WK_ERR_INVALID_ARG, "NULL jb or fields for instance %d", i);
-        descs[i] = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], ws, d_counters);
-        ws += a256(real_size(pl->p) * 4 * pl->np);
+        descs[i] = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], d_counters);
     }
     // cold instances run on the warm path when the batch mixes both
     bool any_warm = false;
@@ -339,12 +333,15 @@ wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void
     const size_t need = wk_batch_workspace_size(n, h_plans);
     if (need == 0 || workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace too small");
     int max_nodes = 0, threads = 256;
+    int64_t max_np = 0;
     bool warm = false;
     for (int i = 0; i < n; ++i) {
         max_nodes = std::max(max_nodes, h_plans[i]->N1);
         threads = std::max(threads, h_plans[i]->shape.threads);
+        max_np = std::max(max_np, h_plans[i]->np);
         warm |= h_plans[i]->p.u_th > 0.0;
     }
+    const bool resident = max_np <= (int64_t)threads * wk::march_tile();
     const size_t lds = wk::march_lds_bytes(max_nodes, threads);
     int per_cu = (int)std::min<size_t>(2, (160 * 1024) / std::max<size_t>(lds, 1));
     if (threads > 1024 / per_cu) per_cu = std::max(1, 2048 / threads / 2);
@@ -363,8 +360,93 @@ wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void
     if (e != hipSuccess) return hip_status(e, "batch queue");
     wk::MarchShape shape{threads, 4};
     return hip_status(wk::launch_march_batch((const wk::MarchDesc*)d_desc, n, max_nodes, h_plans[0]->p.geom,
-                                             warm ? 1 : 0, h_plans[0]->p.prec, shape, grid, next, s),
+                                             warm ? 1 : 0, h_plans[0]->p.prec, shape, resident, grid, next, s),
                       "batch response");
+}
+
+namespace {
+
+int device_cus()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    return cus;
+}
+
+struct CycleLayout {
+    int grid;
+    size_t count, start, fill, order, progress, ticket, plasma, total;
+};
+
+CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
+{
+    CycleLayout L;
+    const int nb = pl->p.n_xi + 1;
+    const size_t lds = wk::cycle_lds_bytes(pl->N1);
+    const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+    L.grid = std::min(n_steps + 1, device_cus() * std::min(per_cu, 2048 / pl->shape.threads));
+    size_t o = 0;
+    L.count = o; o += a256(sizeof(unsigned) * nb);
+    L.start = o; o += a256(sizeof(unsigned) * 2 * (nb + 1));
+    L.fill = o; o += a256(sizeof(unsigned) * nb);
+    L.order = o; o += a256(sizeof(unsigned) * 2 * (size_t)std::max<int64_t>(pl->p.n_beam, 1));
+    L.progress = o; o += a256(sizeof(unsigned) * (size_t)std::max(n_steps, 1));
+    L.ticket = o; o += 256;
+    L.plasma = o; o += a256(sizeof(double) * 4 * (size_t)pl->np * (size_t)L.grid);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps)
+{
+    if (!plan || n_steps < 1) return 0;
+    return cycle_layout(plan, n_steps).total;
+}
+
+wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_beam_bufs* beam, int32_t n_steps,
+                   double dt, void* d_ring, void* d_workspace, size_t workspace_bytes, uint64_t* d_counters,
+                   void* stream)
+{
+    if (!plan || !d_ring || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (n_steps < 1 || !std::isfinite(dt)) return fail(WK_ERR_INVALID_ARG, "bad n_steps or dt");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
+    st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    if (wk::cycle_lds_bytes(plan->N1) > 160 * 1024)
+        return fail(WK_ERR_UNSUPPORTED, "n_r = %d is too large for the pipelined cycle", plan->N);
+    const CycleLayout L = cycle_layout(plan, n_steps);
+    if (workspace_bytes < L.total) return fail(WK_ERR_BUFFER, "cycle workspace needs %zu bytes", L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_workspace;
+    const wk::GridDesc g = grid_of(plan);
+    hipError_t e = wk::launch_zero_u32((unsigned*)(ws + L.progress), (int64_t)(L.plasma - L.progress) / 4, s);
+    if (e != hipSuccess) return hip_status(e, "cycle init");
+    e = wk::launch_beam_bins(g, plan->p.n_beam, *beam, (unsigned*)(ws + L.count), (unsigned*)(ws + L.start),
+                             (unsigned*)(ws + L.fill), (unsigned*)(ws + L.order), s);
+    if (e != hipSuccess) return hip_status(e, "cycle binning");
+    wk::CycleDesc c;
+    c.base = make_desc(plan, plasma, nullptr, nullptr, d_counters);
+    c.beam = *beam;
+    c.grid = g;
+    c.bin_start = (unsigned*)(ws + L.start);
+    c.order = (unsigned*)(ws + L.order);
+    c.n_beam = plan->p.n_beam;
+    c.progress = (unsigned*)(ws + L.progress);
+    c.ticket = (unsigned*)(ws + L.ticket);
+    c.abort_flag = (unsigned long long*)(d_counters + WK_CNT_PIPELINE_ABORT);
+    c.plasma_ws = (double*)(ws + L.plasma);
+    c.ring = d_ring;
+    c.slot_elems = (int64_t)4 * plan->p.n_xi * plan->N1;
+    c.n_steps = n_steps;
+    c.dt = dt;
+    return hip_status(wk::launch_cycle(c, plan->p.prec, plan->shape.threads, L.grid, s), "cycle");
 }
 
 wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields, int32_t n_steps,

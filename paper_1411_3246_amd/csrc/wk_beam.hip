@@ -1,5 +1,5 @@
 // Loaders (a1), beam current (a2), beam push (a9) and diagnostics (a10).
-#include "wk_internal.h"
+#include "wk_beam_dev.h"
 
 namespace wk {
 namespace {
@@ -220,6 +220,21 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const unsigned int* count,
     if (tid == 0) start[n] = carry;
 }
 
+__global__ void k_bin_count(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(count + dev::beam_xi_bin(g, b.d_xi[i]), 1u);
+}
+
+__global__ void k_bin_scatter(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* fill, unsigned int* order)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned int pos = atomicAdd(fill + dev::beam_xi_bin(g, b.d_xi[i]), 1u);
+    order[pos] = (unsigned int)i;
+}
+
 __global__ void k_beam_scatter(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* fill,
                                unsigned int* order)
 {
@@ -277,72 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_beam_push(GridDesc g, int64_t n, wk_
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int N1 = g.n_r + 1;
-    const int64_t plane = (int64_t)g.n_xi * N1;
-    const R* fez = fields + plane;
-    const R* fb = fields + 2 * plane;
-    const R* fw = fields + 3 * plane;
-    const double xi_max = g.xi_min + g.n_xi * g.dxi;
     double x = b.d_x[i], y = b.d_y[i], xi = b.d_xi[i];
     double px = b.d_px[i], py = b.d_py[i], pz = b.d_pz[i];
-    const double qh = -0.5 * dt;
-    unsigned long long out = 0;
-    for (int s = 0; s < n_steps; ++s) {
-        const double r = g.geom == WK_CYL ? sqrt(x * x + y * y) : fabs(x);
-        double ez = 0.0, bt = 0.0, wv = 0.0;
-        if (r <= g.r_max && xi >= g.xi_min && xi < xi_max) {
-            int j;
-            double tr;
-            hat(g, r, j, tr);
-            const double u = (xi - g.xi_min) / g.dxi;
-            int k = (int)floor(u);
-            if (k > g.n_xi - 1) k = g.n_xi - 1;
-            const double tk = u - k;
-            const int k1 = k + 1 < g.n_xi ? k + 1 : k;
-            const double tk1 = k + 1 < g.n_xi ? tk : 0.0;
-            const double w00 = (1.0 - tr) * (1.0 - tk1), w01 = tr * (1.0 - tk1);
-            const double w10 = (1.0 - tr) * tk1, w11 = tr * tk1;
-            const int64_t o0 = (int64_t)k * N1 + j, o1 = (int64_t)k1 * N1 + j;
-            ez = w00 * (double)fez[o0] + w01 * (double)fez[o0 + 1] + w10 * (double)fez[o1] +
-                 w11 * (double)fez[o1 + 1];
-            bt = w00 * (double)fb[o0] + w01 * (double)fb[o0 + 1] + w10 * (double)fb[o1] +
-                 w11 * (double)fb[o1 + 1];
-            wv = w00 * (double)fw[o0] + w01 * (double)fw[o0 + 1] + w10 * (double)fw[o1] +
-                 w11 * (double)fw[o1 + 1];
-        } else {
-            ++out;
-        }
-        const double er = wv + bt;
-        double ux, uy;
-        if (g.geom == WK_CYL) {
-            ux = r > 0.0 ? x / r : 0.0;
-            uy = r > 0.0 ? y / r : 0.0;
-        } else {
-            ux = x < 0.0 ? -1.0 : 1.0;
-            uy = 0.0;
-        }
-        const double Ex = er * ux, Ey = er * uy, Ez = ez;
-        const double Bx = -bt * uy, By = bt * ux;
-        double mx = px + qh * Ex, my = py + qh * Ey, mz = pz + qh * Ez;
-        const double gm = sqrt(1.0 + mx * mx + my * my + mz * mz);
-        const double tx = qh * Bx / gm, ty = qh * By / gm, tz = 0.0;
-        const double t2 = tx * tx + ty * ty + tz * tz;
-        const double qx = mx + (my * tz - mz * ty);
-        const double qy = my + (mz * tx - mx * tz);
-        const double qz = mz + (mx * ty - my * tx);
-        const double sx = 2.0 * tx / (1.0 + t2), sy = 2.0 * ty / (1.0 + t2), sz = 2.0 * tz / (1.0 + t2);
-        const double nx = mx + (qy * sz - qz * sy);
-        const double ny = my + (qz * sx - qx * sz);
-        const double nz = mz + (qx * sy - qy * sx);
-        px = nx + qh * Ex;
-        py = ny + qh * Ey;
-        pz = nz + qh * Ez;
-        const double pp2 = px * px + py * py;
-        const double gam = sqrt(1.0 + pp2 + pz * pz);
-        x = x + dt * px / gam;
-        y = y + dt * py / gam;
-        xi = xi + dt * (1.0 + pp2) / (gam * (gam + pz));
-    }
+    const unsigned long long out = dev::beam_push_particle<R>(g, fields, x, y, xi, px, py, pz, n_steps, dt);
     b.d_x[i] = x;
     b.d_y[i] = y;
     b.d_xi[i] = xi;
@@ -529,6 +481,20 @@ hipError_t launch_beam_current(const GridDesc& g, int64_t n_beam, const wk_beam_
     }
     const size_t lds = sizeof(double) * (g.n_r + 1);
     hipLaunchKernelGGL(k_beam_rows, dim3(g.n_xi), dim3(kBlock), lds, s, g, b, start, order, jb);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_bins(const GridDesc& g, int64_t n_beam, const wk_beam_bufs& b, unsigned int* count,
+                            unsigned int* bin_start, unsigned int* fill, unsigned int* order, hipStream_t s)
+{
+    const int nb = g.n_xi + 1;
+    hipError_t e = launch_zero_u32(count, nb, s);
+    if (e != hipSuccess) return e;
+    if (n_beam > 0)
+        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, b, count);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, count, nb, bin_start, fill);
+    if (n_beam > 0)
+        hipLaunchKernelGGL(k_bin_scatter, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, b, fill, order);
     return hipGetLastError();
 }
 

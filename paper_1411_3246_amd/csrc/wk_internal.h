@@ -28,23 +28,24 @@ struct MarchDesc {
     const double* nion;  // double[n_r+1]
     const double* jb;    // double[n_xi][n_r+1]
     void* fields;        // real[4][n_xi][n_r+1]
-    void* fk;            // real[4][np] stage-1 derivative scratch
     unsigned long long* counters;
     int64_t cost;        // np * n_xi (scheduling weight)
 };
 
-// LDS rows used by the march kernel (each of `stride` doubles).
+// LDS rows used by the march kernel (each of `stride` doubles): the deposit
+// rows, the field rows of both Heun stages, the ion density and the scratch
+// of the tridiagonal solve.
 enum MarchRow {
     ROW_S = 0, ROW_JR, ROW_JZ, ROW_M1, ROW_M2, ROW_M3, ROW_M4, ROW_M5,
-    ROW_PSI, ROW_DPSI, ROW_EZ, ROW_B, ROW_NION,
-    ROW_PA, ROW_PB, ROW_PC, ROW_PD,   // tridiagonal buffer 0
+    ROW_PSI1, ROW_DPSI1, ROW_B1, ROW_PSI2, ROW_DPSI2, ROW_B2, ROW_EZ, ROW_NION,
+    ROW_TU, ROW_TV, ROW_TW,
     NUM_ROWS
 };
 
-inline int lds_stride(int n_nodes) { return (n_nodes + 1) & ~1; }
-inline size_t march_lds_bytes(int n_nodes, int threads)
+__host__ __device__ inline int lds_stride(int n_nodes) { return (n_nodes + 1) & ~1; }
+inline size_t march_lds_bytes(int n_nodes, int /*threads*/)
 {
-    return (size_t)NUM_ROWS * lds_stride(n_nodes) * sizeof(double) + (size_t)(threads / 64 + 2) * sizeof(double);
+    return (size_t)NUM_ROWS * lds_stride(n_nodes) * sizeof(double);
 }
 
 // Launch shapes (chosen by the plan).
@@ -55,8 +56,10 @@ struct MarchShape {
 
 hipError_t launch_march(const MarchDesc& d, int prec, MarchShape shape, hipStream_t stream);
 hipError_t launch_march_batch(const MarchDesc* d_descs, int n, int max_nodes, int geom, int warm,
-                              int prec, MarchShape shape, int grid, unsigned int* d_next,
-                              hipStream_t stream);
+                              int prec, MarchShape shape, bool resident, int grid,
+                              unsigned int* d_next, hipStream_t stream);
+// particles per thread per tile of the march kernel
+int march_tile();
 
 // Beam / loader kernels (wk_beam.hip)
 struct GridDesc {
@@ -85,5 +88,30 @@ hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t s);
 
 // Workspace layout of the beam binning (bytes, 256-aligned pieces).
 size_t beam_ws_bytes(int n_xi, int64_t n_beam);
+
+// Bin the beam by xi cell (bin n_xi: outside the window): bin_start has
+// n_xi + 2 entries, order n_beam.  count/fill are scratch of n_xi + 1.
+hipError_t launch_beam_bins(const GridDesc& g, int64_t n_beam, const wk_beam_bufs& b, unsigned int* count,
+                            unsigned int* bin_start, unsigned int* fill, unsigned int* order, hipStream_t s);
+
+// Pipelined quasi-static cycle (wk_cycle.hip).
+struct CycleDesc {
+    MarchDesc base;                  // plasma template (loaded), constants, counters
+    wk_beam_bufs beam;
+    GridDesc grid;
+    unsigned int* bin_start;         // [2][n_xi + 2], slot 0 filled by launch_beam_bins
+    unsigned int* order;             // [2][n_beam]
+    int64_t n_beam;
+    unsigned int* progress;          // n_steps counters (zeroed)
+    unsigned int* ticket;            // zeroed
+    unsigned long long* abort_flag;  // counter slot, zeroed
+    double* plasma_ws;               // grid * 4 * np doubles
+    void* ring;                      // 2 field slots
+    int64_t slot_elems;
+    int n_steps;
+    double dt;
+};
+size_t cycle_lds_bytes(int n_nodes);
+hipError_t launch_cycle(const CycleDesc& c, int prec, int threads, int grid, hipStream_t s);
 
 }  // namespace wk

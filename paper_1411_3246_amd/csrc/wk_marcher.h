@@ -1,0 +1,753 @@
+// Device-side march of one plasma response (shared by the single, batched and
+// pipelined launches).  Internal header of libwake.
+#pragma once
+
+#include "wk_internal.h"
+
+namespace wk {
+namespace dev {
+
+// --------------------------------------------------------------------------
+// Reciprocals and square roots
+// --------------------------------------------------------------------------
+// Double reciprocal: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ R frcp(R x);
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.0 / x; }
+template <typename R> __device__ __forceinline__ R fsqrt(R x);
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
+
+// --------------------------------------------------------------------------
+// Wave-level prefix sums with DPP row shifts and row broadcasts
+// --------------------------------------------------------------------------
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_prefix(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ double lane63(double v)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier(); }
+
+// Exclusive prefix sums of g(j), j = 0..n-1, by one wavefront in rounds of
+// 64 consecutive items (lane l holds item 64 r + l).  fn(j, excl, incl) is
+// called for every item; returns the total.
+template <class G, class Fn>
+__device__ __forceinline__ double wave_scan_rounds(int n, int lane, const G& g, const Fn& fn)
+{
+    double carry = 0.0;
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + lane;
+        const double v = j < n ? g(j) : 0.0;
+        const double incl = wave_prefix(v);
+        if (j < n) fn(j, carry + incl - v, carry + incl);
+        carry += lane63(incl);
+    }
+    return carry;
+}
+
+// Parallel cyclic reduction by the whole workgroup of the tridiagonal system
+// with rows (a, b, c, d) in buffer 0 (a[0] and c[n-1] ignored); buffer 1 is
+// scratch.  Solution in x.  One barrier per reduction step.
+__device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, double* d0, double* a1, double* b1,
+                          double* c1, double* d1, double* x, int n)
+{
+    const int T = blockDim.x, tid = threadIdx.x;
+    for (int s = 1; s < n; s <<= 1) {
+        for (int i = tid; i < n; i += T) {
+            double na = 0.0, nb = b0[i], nc = 0.0, nd = d0[i];
+            if (i - s >= 0) {
+                const double k1 = a0[i] * rcp64(b0[i - s]);
+                na = -a0[i - s] * k1;
+                nb -= c0[i - s] * k1;
+                nd -= d0[i - s] * k1;
+            }
+            if (i + s < n) {
+                const double k2 = c0[i] * rcp64(b0[i + s]);
+                nc = -c0[i + s] * k2;
+                nb -= a0[i + s] * k2;
+                nd -= d0[i + s] * k2;
+            }
+            a1[i] = na;
+            b1[i] = nb;
+            c1[i] = nc;
+            d1[i] = nd;
+        }
+        __syncthreads();
+        double* t;
+        t = a0; a0 = a1; a1 = t;
+        t = b0; b0 = b1; b1 = t;
+        t = c0; c0 = c1; c1 = t;
+        t = d0; d0 = d1; d1 = t;
+    }
+    for (int i = tid; i < n; i += T) x[i] = d0[i] * rcp64(b0[i]);
+}
+
+// --------------------------------------------------------------------------
+// Per-particle geometry
+// --------------------------------------------------------------------------
+template <typename R>
+struct Rad {
+    int j;      // hat cell
+    R t;        // hat weight of node j+1
+    R rho;      // radius used for deposit/gather (folded at the wall)
+    R sw;       // -1 beyond the wall
+    R sg;       // parity of radial vectors (slab: sign(x) * sw)
+    R r;        // unfolded radius
+};
+
+template <typename R, int GEOM, bool WARM>
+__device__ __forceinline__ Rad<R> radial(double xd, double yd, R rmax, R h, R inv_h, int N)
+{
+    Rad<R> q;
+    const R x = (R)xd;
+    R r;
+    if (GEOM == WK_CYL && WARM) {
+        const R y = (R)yd;
+        r = fsqrt(x * x + y * y);
+    } else {
+        r = fabs(x);
+    }
+    q.r = r;
+    R rho = r, sw = (R)1;
+    if (r > rmax) {
+        sw = (R)-1;
+        rho = (R)2 * rmax - r;
+        if (rho < (R)0) rho = (R)0;
+    }
+    q.rho = rho;
+    q.sw = sw;
+    q.sg = (GEOM == WK_SLAB) ? ((x < (R)0) ? -sw : sw) : sw;
+    // the double path divides like the oracle; the float path multiplies
+    const R u = sizeof(R) == 8 ? rho / h : rho * inv_h;
+    int j = (int)floor(u);
+    j = j < 0 ? 0 : (j > N - 1 ? N - 1 : j);
+    q.j = j;
+    q.t = u - (R)j;
+    return q;
+}
+
+template <typename R>
+__device__ __forceinline__ R gather(const double* row, const Rad<R>& q)
+{
+    return ((R)1 - q.t) * (R)row[q.j] + q.t * (R)row[q.j + 1];
+}
+
+template <typename R>
+struct Part {
+    double x, y, px, py;
+    R d0, w;
+};
+
+struct Deriv {
+    double fx, fy, fpx, fpy;
+};
+
+// Register accumulator of NR deposit rows for the current cell of a thread.
+template <typename R, int NR>
+struct Acc {
+    int j;
+    R lo[NR], hi[NR];
+    __device__ __forceinline__ void reset(int jj)
+    {
+        j = jj;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            lo[r] = (R)0;
+            hi[r] = (R)0;
+        }
+    }
+    __device__ __forceinline__ void add(int r, const Rad<R>& q, R v)
+    {
+        lo[r] += v * ((R)1 - q.t);
+        hi[r] += v * q.t;
+    }
+    // Add the sums to NR consecutive LDS rows starting at `first` (row r at
+    // first + r * stride); row `skip` is left out.
+    __device__ __forceinline__ void flush(double* first, int stride, int skip = -1) const
+    {
+        if (j < 0) return;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r != skip) {
+                atomicAdd(first + r * stride + j, (double)lo[r]);
+                atomicAdd(first + r * stride + j + 1, (double)hi[r]);
+            }
+        }
+    }
+};
+
+template <typename R, int GEOM, bool WARM, int K, bool RESIDENT>
+struct Marcher {
+    const MarchDesc d;
+    double* sm;
+    int st, N, N1, T, tid, lane, wid, blk;
+    double h;
+    R hR, ihR, rmaxR, dminR;
+    unsigned long long clamps, walls;
+    // resident state: positions and momenta in registers, D0 and w in LDS
+    // (slot m * threads + tid)
+    double X[RESIDENT ? K : 1], Y[RESIDENT ? K : 1], PX[RESIDENT ? K : 1], PY[RESIDENT ? K : 1];
+    R* cd0;
+    R* cw;
+
+    // pconst: LDS for the resident D0 and w (2 * threads * K reals)
+    __device__ __forceinline__ Marcher(const MarchDesc& desc, double* smem, void* pconst = nullptr)
+        : d(desc), sm(smem), clamps(0), walls(0)
+    {
+        cd0 = (R*)pconst;
+        cw = cd0 ? cd0 + (int64_t)blockDim.x * K : nullptr;
+        N = d.n_r;
+        N1 = N + 1;
+        st = (N1 + 1) & ~1;
+        T = blockDim.x;
+        tid = threadIdx.x;
+        lane = tid & 63;
+        wid = tid >> 6;
+        h = d.h;
+        hR = (R)d.h;
+        ihR = (R)(1.0 / d.h);
+        rmaxR = (R)d.r_max;
+        dminR = (R)d.d_min;
+    }
+
+    __device__ __forceinline__ double* row(int r) const { return sm + r * st; }
+
+    __device__ __forceinline__ Part<R> load(int64_t i) const
+    {
+        Part<R> p;
+        p.x = d.x[i];
+        p.px = d.px[i];
+        p.y = (GEOM == WK_CYL && WARM) ? d.y[i] : 0.0;
+        p.py = WARM ? d.py[i] : 0.0;
+        p.d0 = ((const R*)d.d0)[i];
+        p.w = ((const R*)d.w)[i];
+        return p;
+    }
+
+    __device__ __forceinline__ void store_state(int64_t i, const Part<R>& p) const
+    {
+        d.x[i] = p.x;
+        d.px[i] = p.px;
+        if (GEOM == WK_CYL && WARM) {
+            d.y[i] = p.y;
+            d.py[i] = p.py;
+        }
+    }
+
+    __device__ __forceinline__ static Part<R> advance(const Part<R>& p, const Deriv& g, double dt)
+    {
+        Part<R> q = p;
+        q.x = p.x + dt * g.fx;
+        q.px = p.px + dt * g.fpx;
+        if (GEOM == WK_CYL && WARM) {
+            q.y = p.y + dt * g.fy;
+            q.py = p.py + dt * g.fpy;
+        }
+        return q;
+    }
+
+    // Eqs. (4)-(5) in the transverse Cartesian frame, with the field rows of
+    // one stage (psi, psi', B_theta).
+    __device__ __forceinline__ Deriv derivative(const Part<R>& p, const double* psi, const double* dpsi,
+                                const double* bt) const
+    {
+        const Rad<R> q = radial<R, GEOM, WARM>(p.x, p.y, rmaxR, hR, ihR, N);
+        R D = p.d0 + gather(psi, q);
+        if (D < dminR) D = dminR;
+        const R px = (R)p.px;
+        const R py = WARM ? (R)p.py : (R)0;
+        const R p2 = px * px + py * py;
+        const R iD = frcp(D);
+        const R gam = ((R)1 + p2 + D * D) * ((R)0.5 * iD);
+        const R F = (gam * iD) * gather(dpsi, q) - gather(bt, q);
+        Deriv g;
+        g.fx = (double)(px * iD);
+        if (GEOM == WK_CYL) {
+            g.fy = WARM ? (double)(py * iD) : 0.0;
+            if (q.r > (R)0) {
+                const R fr = q.sw * F * frcp(q.r);
+                g.fpx = (double)(fr * (R)p.x);
+                g.fpy = WARM ? (double)(fr * (R)p.y) : 0.0;
+            } else {
+                g.fpx = 0.0;
+                g.fpy = 0.0;
+            }
+        } else {
+            g.fy = 0.0;
+            g.fpx = (double)(q.sg * F);
+            g.fpy = 0.0;
+        }
+        return g;
+    }
+
+    __device__ __forceinline__ void reflect(Part<R>& p)
+    {
+        const double rmax = d.r_max;
+        if (GEOM == WK_CYL) {
+            const double r = WARM ? sqrt(p.x * p.x + p.y * p.y) : fabs(p.x);
+            if (r > rmax) {
+                double rn = 2.0 * rmax - r;
+                if (rn < 0.0) rn = 0.0;
+                const double ux = p.x / r, uy = WARM ? p.y / r : 0.0;
+                const double pr = ux * p.px + uy * p.py;
+                p.x = rn * ux;
+                p.px -= 2.0 * pr * ux;
+                if (WARM) {
+                    p.y = rn * uy;
+                    p.py -= 2.0 * pr * uy;
+                }
+                ++walls;
+            }
+        } else {
+            const double ax = fabs(p.x);
+            if (ax > rmax) {
+                double xn = 2.0 * rmax - ax;
+                if (xn < 0.0) xn = 0.0;
+                p.x = p.x < 0.0 ? -xn : xn;
+                p.px = -p.px;
+                ++walls;
+            }
+        }
+    }
+
+    // ---- deposits ------------------------------------------------------------
+    __device__ __forceinline__ void dep_S(Acc<R, 1>& a, const Part<R>& p)
+    {
+        const Rad<R> q = radial<R, GEOM, WARM>(p.x, p.y, rmaxR, hR, ihR, N);
+        if (q.j != a.j) {
+            a.flush(row(ROW_S), st);
+            a.reset(q.j);
+        }
+        a.add(0, q, p.w);
+    }
+
+    // Eqs. (1)-(3): D = D0 + psi, gamma, p_z; currents and moments of d_xi J_r.
+    __device__ __forceinline__ void dep_moments(Acc<R, 7>& a, const Part<R>& p)
+    {
+        const Rad<R> q = radial<R, GEOM, WARM>(p.x, p.y, rmaxR, hR, ihR, N);
+        R D = p.d0 + gather(row(ROW_PSI2), q);
+        if (D < dminR) {
+            D = dminR;
+            ++clamps;
+        }
+        const R px = (R)p.px;
+        const R py = WARM ? (R)p.py : (R)0;
+        const R p2 = px * px + py * py;
+        const R iD = frcp(D);
+        const R h2D = (R)0.5 * iD;
+        const R gam = ((R)1 + p2 + D * D) * h2D;
+        const R pz = ((R)1 + p2 - D * D) * h2D;
+        R pr;
+        if (GEOM == WK_CYL) {
+            const R x = (R)p.x;
+            if (WARM) {
+                const R y = (R)p.y;
+                pr = q.r > (R)0 ? q.sw * (x * px + y * py) * frcp(q.r) : (R)0;
+            } else {
+                pr = q.r > (R)0 ? q.sw * (x * px) * frcp(q.r) : (R)0;
+            }
+        } else {
+            pr = q.sg * px;
+        }
+        if (q.j != a.j) {
+            flush_moments(a);
+            a.reset(q.j);
+        }
+        const R w = p.w;
+        const R wiD = w * iD;
+        const R wiD2 = wiD * iD;
+        a.add(0, q, -wiD * pr);
+        a.add(1, q, -wiD * pz);
+        a.add(2, q, wiD);
+        a.add(3, q, wiD2 * (gam - pr * pr * iD));
+        if (GEOM == WK_CYL && WARM) {
+            if (q.rho > (R)0) {
+                const R l = (R)p.x * py - (R)p.y * px;
+                const R ir = frcp(q.rho);
+                a.add(4, q, wiD2 * (l * l) * (ir * ir * ir));
+            }
+        }
+        a.add(5, q, wiD2 * pr);
+        a.add(6, q, wiD2 * pr * pr);
+    }
+
+    // rows JR, JZ, M1, M2, M3, M4, M5 are consecutive; M3 only for warm
+    // cylindrical plasma
+    __device__ __forceinline__ void flush_moments(const Acc<R, 7>& a)
+    {
+        a.flush(row(ROW_JR), st, (GEOM == WK_CYL && WARM) ? -1 : ROW_M3 - ROW_JR);
+    }
+
+    // ---- solves ----------------------------------------------------------------
+    // 1 / V_j of the hat volumes.
+    __device__ __forceinline__ double inv_volume(int j) const
+    {
+        if (GEOM == WK_CYL) {
+            if (j == 0) return 3.0 * rcp64(kPi * h * h);
+            if (j == N) return rcp64(kPi * h * h * ((double)N - 1.0 / 3.0));
+            return rcp64(2.0 * kPi * (double)j * h * h);
+        }
+        return (j == 0 || j == N) ? 2.0 * rcp64(h) : rcp64(h);
+    }
+
+    // Wave 0: S -> psi.  Gauss fluxes F_{j+1/2} (prefix sum over the control
+    // volumes), u_j = -h F_{j+1/2} / r_{j+1/2}^a, psi_j = sum_{m >= j} u_m
+    // (psi_N = 0); then the node derivative psi'.
+    __device__ __forceinline__ void solve_psi(double* psi, double* dpsi)
+    {
+        const double* S = row(ROW_S);
+        const double* nion = row(ROW_NION);
+        const double c0 = GEOM == WK_CYL ? h * h / 8.0 : 0.5 * h;
+        wave_scan_rounds(
+            N, lane,
+            [&](int j) {
+                const double s = S[j] * inv_volume(j);
+                return j == 0 ? (s - nion[0]) * c0 : (s - nion[j]) * (GEOM == WK_CYL ? (double)j * h : 1.0) * h;
+            },
+            [&](int j, double, double incl) {
+                const double irph = GEOM == WK_CYL ? rcp64(((double)j + 0.5) * h) : 1.0;
+                psi[j] = -h * incl * irph;
+            });
+        wave_sync();
+        const double utot = wave_scan_rounds(
+            N, lane, [&](int j) { return psi[j]; }, [&](int j, double excl, double) { psi[j] = excl; });
+        wave_sync();
+        for (int j = lane; j < N1; j += 64) psi[j] = j < N ? utot - psi[j] : 0.0;
+        wave_sync();
+        const double ih = rcp64(h);
+        for (int j = lane; j < N1; j += 64) {
+            double v;
+            if (j == 0) v = 0.0;
+            else if (j == N) v = (psi[N] - psi[N - 1]) * ih;
+            else v = (psi[j + 1] - psi[j - 1]) * (0.5 * ih);
+            dpsi[j] = v;
+        }
+    }
+
+    // All threads: divide the deposits by the node volumes, add the beam current.
+    __device__ __forceinline__ void finalize_moments(const double* jb_row)
+    {
+        for (int j = tid; j < N1; j += T) {
+            const double iv = inv_volume(j);
+            for (int r = ROW_JR; r <= ROW_M5; ++r) row(r)[j] = row(r)[j] * iv;
+            row(ROW_JZ)[j] += jb_row[j];
+        }
+    }
+
+    // Wave 0: E_z = -int_r^{r_max} J_r dr' (Eq. (7), trapezoid rule).
+    __device__ __forceinline__ void solve_ez(double* ez)
+    {
+        const double* jr = row(ROW_JR);
+        const double tot = wave_scan_rounds(
+            N, lane, [&](int j) { return -(0.5 * h * (jr[j] + jr[j + 1])); },
+            [&](int j, double excl, double) { ez[j] = excl; });
+        wave_sync();
+        for (int j = lane; j < N1; j += 64) ez[j] = j < N ? tot - ez[j] : 0.0;
+    }
+
+    // All threads: B_theta from the Helmholtz form of Eq. (6) (rows 1..N-1) and
+    // Eq. (6) at the wall (row N), by parallel cyclic reduction; then zero the
+    // deposit rows for the next stage.  Needs a barrier before (E_z ready).
+    __device__ __forceinline__ void solve_b(const double* dpsi, const double* ez, double* bt)
+    {
+        const double a = GEOM == WK_CYL ? 1.0 : 0.0;
+        const double ih = rcp64(h);
+        const double ih2 = ih * ih;
+        const double* jz = row(ROW_JZ);
+        const double* m1 = row(ROW_M1);
+        const double* m2 = row(ROW_M2);
+        const double* m3 = row(ROW_M3);
+        const double* m4 = row(ROW_M4);
+        const double* m5 = row(ROW_M5);
+        double* A = row(ROW_TU);
+        double* B = row(ROW_TV);
+        double* C = row(ROW_TW);
+        double* D = row(ROW_S);
+        for (int i = tid; i < N; i += T) {
+            const int j = i + 1;
+            if (j < N) {
+                const double irj = GEOM == WK_CYL ? rcp64((double)j * h) : 1.0;
+                const double rp = GEOM == WK_CYL ? (double)(j + 1) * h : 1.0;
+                const double rm = GEOM == WK_CYL ? (double)(j - 1) * h : 1.0;
+                A[i] = ih2 - a * (0.5 * ih) * irj;
+                B[i] = -2.0 * ih2 - a * irj * irj - m1[j];
+                C[i] = ih2 + a * (0.5 * ih) * irj;
+                const double m5flux = (rp * m5[j + 1] - rm * m5[j - 1]) * (0.5 * ih) * irj;
+                D[i] = (jz[j + 1] - jz[j - 1]) * (0.5 * ih) - m2[j] * dpsi[j] - (GEOM == WK_CYL ? m3[j] : 0.0)
+                       + m4[j] * ez[j] + (GEOM == WK_CYL ? m5flux : (m5[j + 1] - m5[j - 1]) * (0.5 * ih));
+            } else {
+                const double irh = GEOM == WK_CYL ? rcp64(((double)N - 0.5) * h) : 1.0;
+                const double rNm = GEOM == WK_CYL ? (double)(N - 1) * h : 1.0;
+                const double rN = GEOM == WK_CYL ? (double)N * h : 1.0;
+                A[i] = -rNm * ih * irh;
+                B[i] = rN * ih * irh;
+                C[i] = 0.0;
+                D[i] = 0.5 * (jz[N] + jz[N - 1]);
+            }
+        }
+        __syncthreads();
+        block_pcr(A, B, C, D, row(ROW_M2), row(ROW_M3), row(ROW_M4), row(ROW_M5), bt + 1, N);
+        if (tid == 0) bt[0] = 0.0;
+        __syncthreads();
+        for (int j = tid; j < N1; j += T)
+            for (int r = ROW_S; r <= ROW_M5; ++r) row(r)[j] = 0.0;
+    }
+
+    __device__ __forceinline__ void store_fields(int k, const double* psi, const double* ez, const double* bt,
+                                 const double* dpsi)
+    {
+        R* f = (R*)d.fields;
+        const int64_t plane = (int64_t)d.n_xi * N1;
+        unsigned long long bad = 0;
+        for (int j = tid; j < N1; j += T) {
+            const double v0 = psi[j], v1 = ez[j], v2 = bt[j], v3 = -dpsi[j];
+            const int64_t o = (int64_t)k * N1 + j;
+            f[o] = (R)v0;
+            f[plane + o] = (R)v1;
+            f[2 * plane + o] = (R)v2;
+            f[3 * plane + o] = (R)v3;
+            bad += !isfinite(v0) + !isfinite(v1) + !isfinite(v2) + !isfinite(v3);
+        }
+        if (bad) atomicAdd(d.counters + WK_CNT_NONFINITE, bad);
+    }
+
+    // ---- particle passes ----------------------------------------------------
+    // Run fn(m, part) over this thread's particles; with RESIDENT the
+    // particles live in P[], otherwise each tile is loaded (and stored when
+    // STORE) around the call.
+    // Block of K particles owned by this thread within a tile.  When whole
+    // blocks tile the cells (K divides ppc and the waves cover the blocks of a
+    // cell evenly), consecutive lanes take consecutive cells so that their
+    // deposits land on different LDS banks.
+    __device__ __forceinline__ int block_of(int t) const
+    {
+        const int ppc = (int)(d.np / N);
+        if (ppc % K == 0) {
+            const int hpc = ppc / K;
+            const int W = T >> 6;
+            if (hpc > 1 && W % hpc == 0) {
+                const int l = t & 63, w = t >> 6;
+                return l * hpc + (w % hpc) + (w / hpc) * 64 * hpc;
+            }
+        }
+        return t;
+    }
+
+    template <bool STORE, typename Fn>
+    __device__ __forceinline__ void for_parts(Fn fn)
+    {
+        if (RESIDENT) {
+            const int64_t i0 = (int64_t)blk * K;
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                if (i0 + m < d.np) {
+                    Part<R> p;
+                    p.x = X[m];
+                    p.y = Y[m];
+                    p.px = PX[m];
+                    p.py = PY[m];
+                    p.d0 = cd0[m * T + tid];
+                    p.w = cw[m * T + tid];
+                    fn(p);
+                    if (STORE) {
+                        X[m] = p.x;
+                        Y[m] = p.y;
+                        PX[m] = p.px;
+                        PY[m] = p.py;
+                    }
+                }
+            }
+        } else {
+            const int64_t per_tile = (int64_t)T * K;
+            for (int64_t base = 0; base < d.np; base += per_tile) {
+                const int64_t i0 = base + (int64_t)blk * K;
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int64_t i = i0 + m;
+                    if (i < d.np) {
+                        Part<R> p = load(i);
+                        fn(p);
+                        if (STORE) store_state(i, p);
+                    }
+                }
+            }
+        }
+    }
+
+    // Default hooks: beam current rows read from the descriptor's jb array.
+    struct GlobalJb {
+        __device__ __forceinline__ void before_slice(Marcher&, int) {}
+        __device__ __forceinline__ const double* jb_row(Marcher& m, int k) { return m.d.jb + (int64_t)k * m.N1; }
+        __device__ __forceinline__ void after_store(Marcher&, int) {}
+    };
+
+    __device__ __forceinline__ void run()
+    {
+        GlobalJb hooks;
+        run(hooks);
+    }
+
+    template <class Hooks>
+    __device__ __forceinline__ void run(Hooks& hooks)
+    {
+        const double dxi = d.dxi;
+        const double hd = 0.5 * dxi;
+        double* psi1 = row(ROW_PSI1);
+        double* dpsi1 = row(ROW_DPSI1);
+        double* b1 = row(ROW_B1);
+        double* psi2 = row(ROW_PSI2);
+        double* dpsi2 = row(ROW_DPSI2);
+        double* b2 = row(ROW_B2);
+        double* ez = row(ROW_EZ);
+        for (int j = tid; j < N1; j += T) {
+            row(ROW_NION)[j] = d.nion[j];
+            for (int r = ROW_S; r <= ROW_M5; ++r) row(r)[j] = 0.0;
+        }
+        blk = block_of(tid);
+        if (RESIDENT) {
+            const int64_t i0 = (int64_t)blk * K;
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                Part<R> p = Part<R>{0.0, 0.0, 0.0, 0.0, (R)1, (R)0};
+                if (i0 + m < d.np) p = load(i0 + m);
+                X[m] = p.x;
+                Y[m] = p.y;
+                PX[m] = p.px;
+                PY[m] = p.py;
+                cd0[m * T + tid] = p.d0;
+                cw[m * T + tid] = p.w;
+            }
+        }
+        __syncthreads();
+        {
+            Acc<R, 1> a;
+            a.reset(-1);
+            for_parts<false>([&](Part<R>& p) { dep_S(a, p); });
+            a.flush(row(ROW_S), st);
+        }
+        for (int k = 0; k < d.n_xi; ++k) {
+            hooks.before_slice(*this, k);
+            const double* jb0 = hooks.jb_row(*this, k);
+            // ---- stage 1 at (Y_k, xi_k): psi -> moments -> E_z, B ----
+            __syncthreads();
+            if (wid == 0) solve_psi(psi2, dpsi2);
+            __syncthreads();
+            {
+                Acc<R, 7> a;
+                a.reset(-1);
+                for_parts<false>([&](Part<R>& p) { dep_moments(a, p); });
+                flush_moments(a);
+            }
+            __syncthreads();
+            finalize_moments(jb0);
+            __syncthreads();
+            if (wid == 0) solve_ez(ez);
+            __syncthreads();
+            solve_b(dpsi2, ez, b1);
+            // keep the stage-1 psi, psi' for the derivative recomputed later
+            __syncthreads();
+            for (int j = tid; j < N1; j += T) {
+                psi1[j] = psi2[j];
+                dpsi1[j] = dpsi2[j];
+            }
+            store_fields(k, psi2, ez, b1, dpsi2);
+            hooks.after_store(*this, k);
+            if (k == d.n_xi - 1) break;
+            __syncthreads();
+            // ---- stage 2 at (Y*, xi_{k+1}), Y* = Y_k + dxi f_k ----
+            {
+                Acc<R, 1> a;
+                a.reset(-1);
+                for_parts<false>([&](Part<R>& p) {
+                    dep_S(a, advance(p, derivative(p, psi1, dpsi1, b1), dxi));
+                });
+                a.flush(row(ROW_S), st);
+            }
+            __syncthreads();
+            if (wid == 0) solve_psi(psi2, dpsi2);
+            __syncthreads();
+            {
+                Acc<R, 7> a;
+                a.reset(-1);
+                for_parts<false>([&](Part<R>& p) {
+                    dep_moments(a, advance(p, derivative(p, psi1, dpsi1, b1), dxi));
+                });
+                flush_moments(a);
+            }
+            __syncthreads();
+            finalize_moments(hooks.jb_row(*this, k + 1));
+            __syncthreads();
+            if (wid == 0) solve_ez(ez);
+            __syncthreads();
+            solve_b(dpsi2, ez, b2);
+            __syncthreads();
+            // ---- corrector Y_{k+1} = Y_k + dxi/2 (f_k + f*), deposit S(Y_{k+1}) ----
+            {
+                Acc<R, 1> a;
+                a.reset(-1);
+                for_parts<true>([&](Part<R>& p) {
+                    const Deriv g0 = derivative(p, psi1, dpsi1, b1);
+                    const Deriv g1 = derivative(advance(p, g0, dxi), psi2, dpsi2, b2);
+                    p.x = p.x + hd * (g0.fx + g1.fx);
+                    p.px = p.px + hd * (g0.fpx + g1.fpx);
+                    if (GEOM == WK_CYL && WARM) {
+                        p.y = p.y + hd * (g0.fy + g1.fy);
+                        p.py = p.py + hd * (g0.fpy + g1.fpy);
+                    }
+                    reflect(p);
+                    dep_S(a, p);
+                });
+                a.flush(row(ROW_S), st);
+            }
+        }
+        if (RESIDENT) {
+            const int64_t i0 = (int64_t)blk * K;
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                if (i0 + m < d.np) {
+                    Part<R> p;
+                    p.x = X[m];
+                    p.y = Y[m];
+                    p.px = PX[m];
+                    p.py = PY[m];
+                    store_state(i0 + m, p);
+                }
+        }
+        if (clamps) atomicAdd(d.counters + WK_CNT_D_CLAMP, clamps);
+        if (walls) atomicAdd(d.counters + WK_CNT_WALL, walls);
+    }
+};
+
+
+}  // namespace dev
+}  // namespace wk

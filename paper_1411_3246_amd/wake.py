@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libwake.so")
 
 WK_CYL, WK_SLAB = 0, 1
 WK_FP64, WK_MIXED = 0, 1
-COUNTER_NAMES = ["d_clamp", "wall", "nonfinite", "beam_out_deposit", "beam_out_push", "beam_bin"]
+COUNTER_NAMES = ["d_clamp", "wall", "nonfinite", "beam_out_deposit", "beam_out_push", "beam_bin",
+                 "pipeline_abort"]
 NCOUNTERS = 8
 
 
@@ -66,10 +67,12 @@ EXPORTS = [
     "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
+    "wk_cycle_workspace_size", "wk_cycle",
 ]
 
 _NON_STATUS = {"wk_version", "wk_status_string", "wk_last_error", "wk_plan_destroy",
-               "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size"}
+               "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size",
+               "wk_cycle_workspace_size"}
 
 _lib = None
 
@@ -111,6 +114,10 @@ def lib():
     L.wk_beam_push.argtypes = [vp, C.POINTER(WkBeamBufs), vp, i32, d, vp, vp]
     L.wk_mean_gain.argtypes = [vp, C.POINTER(WkBeamBufs), i32, vp, vp, vp]
     L.wk_ez_peak.argtypes = [vp, vp, d, vp, vp]
+    L.wk_cycle_workspace_size.argtypes = [vp, i32]
+    L.wk_cycle_workspace_size.restype = C.c_size_t
+    L.wk_cycle.argtypes = [vp, C.POINTER(WkPlasmaBufs), C.POINTER(WkBeamBufs), i32, d, vp, vp,
+                           C.c_size_t, vp, vp]
     for name in EXPORTS:
         if name not in _NON_STATUS:
             getattr(L, name).restype = C.c_int
@@ -268,6 +275,17 @@ class Plan:
         _check(lib().wk_mean_gain(self.handle, C.byref(b), which, _ptr(out), _ptr(workspace),
                                   _stream(stream)), "wk_mean_gain")
 
+    def cycle_workspace_bytes(self, n_steps: int) -> int:
+        return lib().wk_cycle_workspace_size(self.handle, n_steps)
+
+    def cycle(self, plasma: Dict, beam: Dict, n_steps: int, dt: float, ring, workspace, counters,
+              stream=None):
+        p = self.plasma_bufs(plasma)
+        b = self.beam_bufs(beam)
+        _check(lib().wk_cycle(self.handle, C.byref(p), C.byref(b), n_steps, dt, _ptr(ring),
+                              _ptr(workspace), workspace.numel(), _ptr(counters), _stream(stream)),
+               "wk_cycle")
+
     def ez_peak(self, fields, xi_from: float, out, stream=None):
         _check(lib().wk_ez_peak(self.handle, _ptr(fields), xi_from, _ptr(out), _stream(stream)),
                "wk_ez_peak")
@@ -376,6 +394,24 @@ class Simulation:
         self.response()
         if self.beam is not None:
             self.push(1)
+
+    def run_cycle(self, n_steps: int, dt: Optional[float] = None):
+        """n_steps quasi-static cycles (current -> response -> push) with the
+        responses of successive steps pipelined across workgroups.  Afterwards
+        `fields` holds the last response."""
+        import torch
+        if self.beam is None:
+            raise WakeError("run_cycle needs beam macroparticles")
+        if getattr(self, "ring", None) is None:
+            self.ring = torch.zeros((2,) + tuple(self.fields.shape), dtype=self.fields.dtype,
+                                    device=self.device)
+        need = self.plan.cycle_workspace_bytes(n_steps)
+        if getattr(self, "cycle_ws", None) is None or self.cycle_ws.numel() < need:
+            self.cycle_ws = torch.zeros(need, dtype=torch.uint8, device=self.device)
+        self.plan.init_plasma(self.plasma, self.plasma_draws)
+        self.plan.cycle(self.plasma, self.beam, n_steps, self.problem.dt if dt is None else dt,
+                        self.ring, self.cycle_ws, self.counters)
+        self.fields = self.ring[(n_steps - 1) % 2]
 
     def witness_gain(self) -> float:
         self.plan.mean_gain(self.beam, 1, self.out[0:1], self.workspace)

@@ -268,3 +268,55 @@ def test_full_size_blowout_first_response_mixed(O, W):
     print("full-size mixed L2 error E_z:", e, flush=True)
     assert e <= 1e-3
     assert sim.counters_dict()["nonfinite"] == 0
+
+
+def _beam_np(sim):
+    return {k: _np(sim.beam[k]) for k in ("x", "y", "px", "py", "pz", "xi")}
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_pipelined_cycle_matches_sequential(O, W, prec):
+    """The pipelined cycle (responses of successive beam steps on separate
+    workgroups) gives the sequential cycle's beam, FP64, moderate driver."""
+    import torch
+    p = inputs.facet_two_bunch(n_r=96, n_xi=400, ppc=8, u_th=0.02, n_d=1.0, n_beam=6000,
+                               n_steps=5, prec=prec)
+    print("case", p.name, "steps", p.n_steps, flush=True)
+    seq = W.Simulation(p)
+    seq.load_beam()
+    for _ in range(p.n_steps):
+        seq.step()
+    torch.cuda.synchronize()
+    pipe = W.Simulation(p)
+    pipe.load_beam()
+    pipe.run_cycle(p.n_steps)
+    torch.cuda.synchronize()
+    c = pipe.counters_dict()
+    assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0
+    a, b = _beam_np(pipe), _beam_np(seq)
+    for k in a:
+        scale = max(1.0, np.max(np.abs(b[k])))
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-10 * scale, k
+    assert _rel(_np(pipe.fields), _np(seq.fields)) <= 1e-10
+    # and the oracle's sequential cycle
+    ref = O.cycle(p, inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
+    for k in ("x", "pz", "xi"):
+        scale = max(1.0, np.max(np.abs(ref["beam"][k])))
+        assert np.max(np.abs(a[k] - ref["beam"][k])) <= 1e-9 * scale, k
+    assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-9)
+
+
+def test_pipelined_cycle_mixed_blowout(O, W):
+    """Blowout two-bunch driver, mixed precision, 8 pipelined steps vs the
+    FP64 oracle: witness gain within 1e-3, no aborts, no bin escapes."""
+    import torch
+    p = inputs.facet_two_bunch(n_r=128, n_xi=1024, ppc=8, u_th=0.02, n_beam=20000, n_steps=8,
+                               prec="mixed")
+    pipe = W.Simulation(p)
+    pipe.load_beam()
+    pipe.run_cycle(p.n_steps)
+    torch.cuda.synchronize()
+    c = pipe.counters_dict()
+    assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0 and c["nonfinite"] == 0
+    ref = O.cycle(p.replace(prec="fp64"), inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
+    assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-3)
