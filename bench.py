@@ -1,15 +1,23 @@
 """Benchmark of the quasi-static plasma-response hot path on one MI355X.
 
-A step is one quasi-static cycle of the headline workload (two-bunch blowout,
-512 x 4096 r-xi grid, 16 ring particles per cell, u_th = 0.02, 1e6-particle
-evolving beam, FP32 bulk with FP64 solves): beam current from the
-macroparticles -> plasma loaded ahead of the beam -> plasma response over
-all 4096 slices -> beam push over dt = 40 -> witness energy-gain diagnostic.
-All inputs are synthetic, seeded and resident in HBM before timing starts.
+Workload: the two-bunch blowout run (512 x 4096 r-xi grid over r <= 6,
+xi in [0, 10), 16 ring particles per cell with u_th = 0.02, drive n_b = 8,
+sigma_r = 0.3, sigma_z = 0.7, witness with 0.3 of its charge 4.5 behind,
+1e6-particle beam at gamma = 4e4 with 0.1 % energy spread, dt = 40), FP32
+bulk with FP64 field solves, deposit accumulation and xi integration.
+Synthetic, seeded inputs resident in HBM before timing starts.
+
+A step is one quasi-static cycle: beam current from the macroparticles ->
+plasma (loaded ahead of the beam) marched through all 4096 slices -> beam
+advanced by dt.  The timed region runs `--steps` cycles from the loaded beam
+as one pipelined launch (responses of successive steps overlap across
+workgroups) plus the witness energy-gain diagnostic.  `--mode sequential`
+times the same cycles one response at a time instead.
 
 Prints one JSON line.  value = plasma particle-slice updates per second
 (n_plasma * (n_xi - 1) per step).  The roofline entry is for the dominant
-kernel (the march), timed with HIP events on the stream it runs on.
+kernel (the cycle kernel, or the march kernel in sequential mode), timed
+with HIP events on the stream it runs on.
 """
 from __future__ import annotations
 
@@ -24,21 +32,46 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# Algorithmic bytes per plasma particle-slice update of the method's state in
-# the mixed mode: (r, p_r) double read + write (32 B) and (l_z, D0, w) float
-# read (12 B).
+# Algorithmic bytes per plasma particle-slice update in the mixed mode: the
+# method's particle state (r, p_r) in double read and written (32 B) and
+# (l_z, D0, w) in float read (12 B) once per slice.
 BYTES_PER_UPDATE = 44.0
+# Scaled FETCH_SIZE + WRITE_SIZE of the cycle kernel, recorded with rocprofv3
+# for a given kernel-source hash; reported only while the sources match.
+COUNTERS = os.path.join(ROOT, "profiles", "k_cycle_two-bunch-512x4096-ppc16-beam1e6.counters.json")
+KERNEL_SOURCES = ("wk_cycle.hip", "wk_marcher.h", "wk_beam_dev.h", "wk_internal.h")
+
+
+def measured_traffic(steps: int):
+    """HBM bytes per launch from the committed counter run, or None when the
+    kernel sources changed since it was taken or the launch differs."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for name in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, "paper_1411_3246_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
+    if h.hexdigest()[:16] != rec.get("source_hash") or rec.get("steps") != steps:
+        return None
+    return rec["traffic_bytes"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mode", choices=["pipelined", "sequential"], default="pipelined")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of one plasma response timed with the CPU oracle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--threads", type=int, default=None, help="march workgroup size override")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -60,8 +93,8 @@ def cpu_baseline(p, fraction: float):
     dt = time.perf_counter() - t0
     upd = q.n_plasma * (n_xi - 1)
     return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 plasma response, {n_xi} of {q.n_xi} slices, {q.n_plasma} particles "
-                      f"per slice ({upd:.3g} updates, {dt:.1f} s, serial C)"}
+            "sample": f"one FP64 plasma response of the same workload, {n_xi} of {q.n_xi} slices, "
+                      f"{q.n_plasma} particles per slice ({upd:.3g} updates, {dt:.1f} s, serial C)"}
 
 
 def main():
@@ -74,40 +107,66 @@ def main():
     from paper_1411_3246_amd import inputs, wake
 
     torch.cuda.set_device(0)
-    p = inputs.blowout_response()
+    p = inputs.blowout_response().replace(n_steps=args.steps)
     sim = wake.Simulation(p, threads=args.threads)
-    sim.load_beam()
     stream = torch.cuda.current_stream()
     upd_per_step = p.updates_per_response()
 
-    def step(ev=None):
-        sim.beam_current()
-        sim.plan.init_plasma(sim.plasma, sim.plasma_draws)
-        if ev is not None:
-            ev[0].record(stream)
-        sim.plan.plasma_response(sim.plasma, sim.jb, sim.fields, sim.workspace, sim.counters)
-        if ev is not None:
-            ev[1].record(stream)
-        sim.push(1)
-        sim.plan.mean_gain(sim.beam, 1, sim.out[0:1], sim.workspace)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
 
-    for _ in range(args.warmup):
-        step()
+    def run(n, ev=None):
+        if args.mode == "pipelined":
+            if ev is not None:
+                ev[0].record(stream)
+            sim.run_cycle(n)
+            if ev is not None:
+                ev[1].record(stream)
+        else:
+            t = 0.0
+            for _ in range(n):
+                sim.beam_current()
+                sim.plan.init_plasma(sim.plasma, sim.plasma_draws)
+                if ev is not None:
+                    ev[0].record(stream)
+                sim.plan.plasma_response(sim.plasma, sim.jb, sim.fields, sim.workspace, sim.counters)
+                if ev is not None:
+                    ev[1].record(stream)
+                    torch.cuda.synchronize()
+                    t += ev[0].elapsed_time(ev[1])
+                sim.push(1)
+            return t
+        return None
+
+    sim.load_beam()
+    if args.warmup > 0:
+        run(args.warmup)
     torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+    sim.load_beam()                       # the timed run starts from the loaded beam
+    wake.zero_counters(sim.counters)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
+    kt = run(args.steps, ev)
+    sim.plan.mean_gain(sim.beam, 1, sim.out[0:1], sim.workspace)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    march_ms = sum(a.elapsed_time(b) for a, b in events) / args.steps
-
-    value = upd_per_step * args.steps / elapsed
+    if args.mode == "pipelined":
+        kernel_ms = ev[0].elapsed_time(ev[1])
+        kernel, launches = "k_cycle", 1
+    else:
+        kernel_ms = kt
+        kernel, launches = "k_march_one", args.steps
+    updates = upd_per_step * args.steps
+    value = updates / elapsed
     counters = sim.counters_dict()
     gain = float(sim.out[0].item())
-    achieved = BYTES_PER_UPDATE * upd_per_step / (march_ms * 1e-3) / 1e9
+    achieved = BYTES_PER_UPDATE * updates / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.steps) if args.mode == "pipelined" else None
     line = {
         "metric": "plasma particle-slice updates/s at 1 GPU",
         "value": value,
@@ -123,12 +182,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.name, "geometry": p.geom, "n_r": p.n_r, "n_xi": p.n_xi,
                    "ppc": p.ppc, "u_th": p.u_th, "n_beam": p.n_beam, "beam_steps_timed": args.steps,
-                   "dt": p.dt, "precision": "FP32 bulk, FP64 solve/accumulation/xi integration",
+                   "dt": p.dt, "mode": args.mode,
+                   "precision": "FP32 bulk; FP64 solves, deposit accumulation and xi integration",
                    "march_threads": sim.plan.threads},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_march_one", "ms_per_launch": march_ms,
-                     "bytes_per_update": BYTES_PER_UPDATE},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kernel, "launches": launches,
+                     "ms_per_launch": kernel_ms / launches,
+                     "bytes_per_update": BYTES_PER_UPDATE,
+                     "traffic_unit": "bytes per launch"},
         "diagnostics": {"witness_mean_gain_gamma": gain, "counters": counters},
     }
     if not args.no_cpu:

@@ -169,7 +169,7 @@ const char* wk_last_error(void);
  * kernel (safe under stream capture). */
 wk_status wk_counters_zero(uint64_t* d_counters, void* stream);
 
-/* a1, plasma: ring macroparticles at cell-uniform radii; with u_th > 0,
+/* Plasma loader: ring macroparticles at cell-uniform radii; with u_th > 0,
  * mirrored pairs with momenta u_th * draws (d_draws: 3 standard normals per
  * pair, pair q = cell * ppc/2 + sub-radius) and flux weights a D0/gamma0;
  * n_ion = deposit of the initial areas (Section II A, Eq. (1) and the
@@ -177,22 +177,22 @@ wk_status wk_counters_zero(uint64_t* d_counters, void* stream);
 wk_status wk_init_plasma(const wk_plan* plan, const wk_plasma_bufs* plasma,
                          const double* d_draws, void* stream);
 
-/* a1, beam: macroparticles sampling Eq. (12) from d_draws (4 standard
+/* Beam loader: macroparticles sampling Eq. (12) from d_draws (4 standard
  * normals per particle: x, y, xi, energy), charge weight Q_bunch / N_bunch. */
 wk_status wk_init_beam(const wk_plan* plan, const wk_beam_bufs* beam,
                        const double* d_draws, void* stream);
 
-/* a2, analytic: J_bz = -n_b(r_j, xi_k) from Eq. (12) (fixed beam). */
+/* Beam current, analytic: J_bz = -n_b(r_j, xi_k) from Eq. (12) (fixed beam). */
 wk_status wk_beam_current_analytic(const wk_plan* plan, double* d_jb, void* stream);
 
-/* a2, macroparticles: J_bz = -sum W hat_j(r) hat_k(xi) / (V_j dxi) with
+/* Beam current, macroparticles: J_bz = -sum W hat_j(r) hat_k(xi) / (V_j dxi) with
  * v_z = c (Section II A: the total current includes the beam current).
  * Uses the workspace for the xi binning of the beam; counts particles
  * outside the window. */
 wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double* d_jb,
                           void* d_workspace, uint64_t* d_counters, void* stream);
 
-/* a3-a8: one plasma response.  Marches the plasma state of `plasma` from
+/* One plasma response.  Marches the plasma state of `plasma` from
  * slice 0 (unperturbed, as loaded) to slice n_xi - 1 with Heun steps,
  * solving psi, E_z and B_theta on every slice and storing
  * d_fields = real[4][n_xi][n_nodes] = psi, E_z, B_theta, W = E_r - B_theta.
@@ -248,17 +248,17 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
                    int32_t n_steps, double dt, void* d_ring, void* d_workspace,
                    size_t workspace_bytes, uint64_t* d_counters, void* stream);
 
-/* a9: advance the beam n_steps times by dt in the frozen fields d_fields
+/* Beam push: advance the beam n_steps times by dt in the frozen fields d_fields
  * (Eqs. (8)-(11), Boris rotation, cancellation-free d xi/dt). */
 wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields,
                        int32_t n_steps, double dt, uint64_t* d_counters, void* stream);
 
-/* a10: charge-weighted mean gamma gain of the particles with tag == which,
+/* Diagnostic: charge-weighted mean gamma gain of the particles with tag == which,
  * written to d_out[0] (deterministic two-level reduction in the
  * workspace). */
 wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which,
                        double* d_out, void* d_workspace, void* stream);
-/* a10: most negative on-axis E_z over slices with xi_k >= xi_from, written
+/* Diagnostic: most negative on-axis E_z over slices with xi_k >= xi_from, written
  * to d_out[0] as double. */
 wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
                      double* d_out, void* stream);

@@ -1,4 +1,4 @@
-// Loaders (a1), beam current (a2), beam push (a9) and diagnostics (a10).
+// Loaders, beam current, beam push and diagnostics.
 #include "wk_beam_dev.h"
 
 namespace wk {
@@ -40,7 +40,7 @@ __global__ void k_zero_u32(unsigned int* p, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// a1: plasma loader (cell-uniform rings; mirrored thermal pairs).  One
+// Plasma loader (cell-uniform rings; mirrored thermal pairs).  One
 // workgroup; n_ion is deposited in LDS and divided by the node volumes.
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(1024) void k_init_plasma(GridDesc g, int ppc, doubl
 }
 
 // ---------------------------------------------------------------------------
-// a1: beam loader (Eq. (12) sampled with the given standard normals)
+// Beam loader (Eq. (12) sampled with the given standard normals)
 // ---------------------------------------------------------------------------
 struct BeamLoad {
     double sigma_r, gamma0, rel;
@@ -127,7 +127,7 @@ __global__ void k_init_beam(BeamLoad L, int64_t n, wk_beam_bufs b, const double*
 }
 
 // ---------------------------------------------------------------------------
-// a2: analytic beam current, J_bz = -n_b of Eq. (12)
+// Analytic beam current, J_bz = -n_b of Eq. (12)
 // ---------------------------------------------------------------------------
 struct BeamShape {
     double sigma_r;
@@ -152,7 +152,7 @@ __global__ void k_beam_current_analytic(GridDesc g, BeamShape s, double* jb)
 }
 
 // ---------------------------------------------------------------------------
-// a2: macroparticle beam current.  The beam is binned by xi cell (counting
+// Macroparticle beam current.  The beam is binned by xi cell (counting
 // sort into an index array in the workspace); one workgroup per slice then
 // gathers the particles of the two adjacent cells into an LDS row.  Every row
 // of J_bz is written by exactly one workgroup (no global float atomics).
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_beam_rows(GridDesc g, wk_beam_bufs b
 }
 
 // ---------------------------------------------------------------------------
-// a9: beam push, Eqs. (8)-(11) with the Boris rotation (q = -1)
+// Beam push, Eqs. (8)-(11) with the Boris rotation (q = -1)
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_beam_push(GridDesc g, int64_t n, wk_beam_bufs b,
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_beam_push(GridDesc g, int64_t n, wk_
 }
 
 // ---------------------------------------------------------------------------
-// a10: diagnostics (deterministic two-level reductions)
+// Diagnostics (deterministic two-level reductions)
 // ---------------------------------------------------------------------------
 constexpr int kGainBlocks = 512;
 
