@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--threads", type=int, default=None, help="march workgroup size override")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the batched 256-instance parameter scan")
+    ap.add_argument("--scan-instances", type=int, default=256)
+    ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
     return ap.parse_args()
 
 
@@ -95,6 +99,65 @@ def cpu_baseline(p, fraction: float):
     return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"one FP64 plasma response of the same workload, {n_xi} of {q.n_xi} slices, "
                       f"{q.n_plasma} particles per slice ({upd:.3g} updates, {dt:.1f} s, serial C)"}
+
+
+def scan_bench(args, log):
+    """The batched parameter scan: every instance of the scan marched in one
+    persistent launch (shape picked by the autotuner, the whole pass replayed
+    from a HIP graph) against the same instances run one launch at a time.
+
+    The one-at-a-time time is measured on every instance with its xi window
+    cut to 128 slices and scaled by (n_xi - 1) / 127: a response costs the
+    same per slice, so this keeps the baseline to a few seconds."""
+    import torch
+    from paper_1411_3246_amd import autotune, inputs, wake
+    probs = inputs.scan_instances(args.scan_instances)
+    scan = wake.Scan(probs)
+    best, table = autotune.tune_scan(scan, log=log)
+    scan.capture()
+    stream = torch.cuda.current_stream()
+    scan.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.scan_reps):
+        scan.replay()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1]) / args.scan_reps
+    counters = wake.counters_dict(scan.counters)
+    updates = scan.updates
+    del scan
+    torch.cuda.empty_cache()
+
+    cut = 128
+    short = wake.Scan([q.replace(n_xi=cut) for q in probs])
+    for i in range(len(probs)):            # warm-up of every kernel variant
+        short.run_one(i)
+    torch.cuda.synchronize()
+    seq_ms = 0.0
+    for i, q in enumerate(probs):
+        ev[0].record(stream)
+        short.run_one(i)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        seq_ms += ev[0].elapsed_time(ev[1]) * (q.n_xi - 1) / (cut - 1)
+    del short
+    torch.cuda.empty_cache()
+    return {
+        "instances": len(probs),
+        "updates": updates,
+        "batched_ms": batched_ms,
+        "batched_updates_per_s": updates / (batched_ms * 1e-3),
+        "sequential_ms_est": seq_ms,
+        "batched_speedup": seq_ms / batched_ms,
+        "shape": {"threads": best[0], "wg_per_cu": best[1]},
+        "tuner": table,
+        "graph": True,
+        "counters": counters,
+        "recipe": "u_th~U[0,0.05], sep~U[3,6], n_r in {128,256,512,1024}, n_xi~U{1024..4096}, "
+                  "ppc in {8..32 even}, fixed analytic two-bunch beam, mixed precision",
+    }
 
 
 def main():
@@ -193,6 +256,10 @@ def main():
                      "traffic_unit": "bytes per launch"},
         "diagnostics": {"witness_mean_gain_gamma": gain, "counters": counters},
     }
+    if not args.no_scan:
+        sc = scan_bench(args, lambda row: print(f"# tuner {row}", file=sys.stderr, flush=True))
+        line["batched_scan"] = sc
+        line["batched_speedup"] = sc["batched_speedup"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
     print(json.dumps(line), flush=True)

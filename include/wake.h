@@ -225,6 +225,14 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans,
                             uint64_t* d_counters, void* h_desc);
 wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc,
                             void* d_workspace, size_t workspace_bytes, void* stream);
+/* The same launch with an explicit shape: threads per workgroup (256, 512 or
+ * 1024; 0 = the largest of the plans' choices) and workgroups per compute
+ * unit (1..8, clamped to what LDS and the 2048-thread limit allow; 0 =
+ * default).  Used by the autotuner; the results do not depend on the shape
+ * beyond the summation order of the deposits. */
+wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, const void* d_desc,
+                                  void* d_workspace, size_t workspace_bytes, int32_t threads,
+                                  int32_t wg_per_cu, void* stream);
 
 /* The quasi-static cycle, n_steps times: beam current from the macroparticles
  * -> plasma response -> beam advance by dt (Section II A: the plasma responds

@@ -1,6 +1,8 @@
 // C ABI of libwake: problem validation, plans, buffer sizes and launches.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +24,21 @@ struct wk_plan {
 };
 
 namespace {
+
+// Compute units of the current device (queried once per device).
+int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev >= 0 && dev < 64 && cache[dev].load() > 0) return cache[dev].load();
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    if (dev >= 0 && dev < 64) cache[dev].store(cus);
+    return cus;
+}
 
 thread_local std::string g_err;
 
@@ -326,34 +343,34 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_p
     return WK_OK;
 }
 
-wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc, void* d_workspace,
-                            size_t workspace_bytes, void* stream)
+wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, const void* d_desc, void* d_workspace,
+                                  size_t workspace_bytes, int32_t threads, int32_t wg_per_cu, void* stream)
 {
     if (n <= 0 || !h_plans || !d_desc || !d_workspace) return fail(WK_ERR_INVALID_ARG, "NULL argument or n <= 0");
     const size_t need = wk_batch_workspace_size(n, h_plans);
     if (need == 0 || workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace too small");
-    int max_nodes = 0, threads = 256;
-    int64_t max_np = 0;
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(WK_ERR_INVALID_ARG, "threads must be 0, 256, 512 or 1024 (got %d)", threads);
+    if (wg_per_cu < 0 || wg_per_cu > 8) return fail(WK_ERR_INVALID_ARG, "wg_per_cu must be 0..8 (got %d)", wg_per_cu);
+    int max_nodes = 0, plan_threads = 256;
+    int64_t min_np = INT64_MAX;
     bool warm = false;
     for (int i = 0; i < n; ++i) {
         max_nodes = std::max(max_nodes, h_plans[i]->N1);
-        threads = std::max(threads, h_plans[i]->shape.threads);
-        max_np = std::max(max_np, h_plans[i]->np);
+        plan_threads = std::max(plan_threads, h_plans[i]->shape.threads);
+        min_np = std::min(min_np, h_plans[i]->np);
         warm |= h_plans[i]->p.u_th > 0.0;
     }
-    const bool resident = max_np <= (int64_t)threads * wk::march_tile();
+    if (threads == 0) threads = plan_threads;
+    // the resident variant (decided per instance in the kernel) when some
+    // instance fits the registers; the launcher drops it if LDS cannot hold it
+    const bool resident = min_np <= (int64_t)threads * wk::march_tile();
     const size_t lds = wk::march_lds_bytes(max_nodes, threads);
-    int per_cu = (int)std::min<size_t>(2, (160 * 1024) / std::max<size_t>(lds, 1));
-    if (threads > 1024 / per_cu) per_cu = std::max(1, 2048 / threads / 2);
-    if (per_cu < 1) per_cu = 1;
-    int cus = 256;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-    }
-    const int grid = std::min(n, cus * per_cu);
+    // workgroups resident per CU: bounded by LDS (160 KB) and by 2048 threads
+    const int fit = (int)std::max<size_t>(1, std::min<size_t>((160 * 1024) / std::max<size_t>(lds, 1),
+                                                               (size_t)(2048 / threads)));
+    int per_cu = wg_per_cu > 0 ? std::min(wg_per_cu, fit) : std::min(fit, threads >= 1024 ? 1 : 2);
+    const int grid = std::min(n, device_cus() * per_cu);
     hipStream_t s = (hipStream_t)stream;
     unsigned int* next = (unsigned int*)d_workspace;
     hipError_t e = wk::launch_zero_u32(next, 1, s);
@@ -364,18 +381,14 @@ wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void
                       "batch response");
 }
 
+wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc, void* d_workspace,
+                            size_t workspace_bytes, void* stream)
+{
+    return wk_batch_response_shape(n, h_plans, d_desc, d_workspace, workspace_bytes, 0, 0, stream);
+}
+
 namespace {
 
-int device_cus()
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-    }
-    return cus;
-}
 
 struct CycleLayout {
     int grid;

@@ -32,6 +32,9 @@ __global__ __launch_bounds__(T) void k_march_one(MarchDesc d)
     m.run();
 }
 
+// Persistent batched march: workgroups take instances from a queue (longest
+// first).  With RES, an instance whose particles fit T * K registers stays
+// resident; larger instances stream their particles in tiles.
 template <typename R, int GEOM, bool WARM, int T, int K, bool RES>
 __global__ __launch_bounds__(T) void k_march_batch(const MarchDesc* __restrict__ descs, int n,
                                                    unsigned int* next)
@@ -45,8 +48,13 @@ __global__ __launch_bounds__(T) void k_march_batch(const MarchDesc* __restrict__
         __syncthreads();
         if (i >= n) break;
         const MarchDesc d = descs[i];
-        Marcher<R, GEOM, WARM, K, RES> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
-        m.run();
+        if (RES && d.np <= (int64_t)T * K) {
+            Marcher<R, GEOM, WARM, K, true> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+            m.run();
+        } else {
+            Marcher<R, GEOM, WARM, K, false> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+            m.run();
+        }
         __syncthreads();
     }
 }

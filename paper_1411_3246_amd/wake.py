@@ -66,7 +66,7 @@ EXPORTS = [
     "wk_last_error", "wk_counters_zero", "wk_init_plasma", "wk_init_beam",
     "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
-    "wk_batch_response", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
+    "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle",
 ]
 
@@ -111,6 +111,7 @@ def lib():
     L.wk_batch_describe.argtypes = [i32, C.POINTER(vp), C.POINTER(WkPlasmaBufs), C.POINTER(vp),
                                     C.POINTER(vp), vp, C.c_size_t, vp, vp]
     L.wk_batch_response.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, vp]
+    L.wk_batch_response_shape.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, i32, i32, vp]
     L.wk_beam_push.argtypes = [vp, C.POINTER(WkBeamBufs), vp, i32, d, vp, vp]
     L.wk_mean_gain.argtypes = [vp, C.POINTER(WkBeamBufs), i32, vp, vp, vp]
     L.wk_ez_peak.argtypes = [vp, vp, d, vp, vp]
@@ -334,12 +335,14 @@ class Batch:
         self.desc.copy_(blob)
         self._described = True
 
-    def response(self, stream=None):
+    def response(self, stream=None, threads: int = 0, wg_per_cu: int = 0):
+        """March every instance; threads / wg_per_cu = 0 keep the defaults."""
         if not self._described:
             raise WakeError("Batch.describe must be called first")
-        _check(lib().wk_batch_response(len(self.plans), self._handles, _ptr(self.desc),
-                                       _ptr(self.workspace), self.ws_bytes, _stream(stream)),
-               "wk_batch_response")
+        _check(lib().wk_batch_response_shape(len(self.plans), self._handles, _ptr(self.desc),
+                                             _ptr(self.workspace), self.ws_bytes, int(threads),
+                                             int(wg_per_cu), _stream(stream)),
+               "wk_batch_response_shape")
 
 
 # ---------------------------------------------------------------------------
@@ -423,3 +426,77 @@ class Simulation:
 
     def counters_dict(self):
         return counters_dict(self.counters)
+
+
+# ---------------------------------------------------------------------------
+# Convenience: a parameter scan of fixed-beam instances in one launch
+# ---------------------------------------------------------------------------
+
+class Scan:
+    """Independent fixed-beam plasma responses (any mix of grid sizes,
+    temperatures and separations; one geometry and precision) with their
+    buffers, run as one persistent batched launch.
+
+    run() loads every plasma and marches all instances; run_one(i) marches
+    instance i alone with the standalone entry point (the per-instance
+    baseline of the batched launch); capture() records run() in a HIP graph."""
+
+    def __init__(self, problems: Sequence[inputs.Problem], device="cuda"):
+        import torch
+        self.problems = list(problems)
+        self.device = device
+        self.plans = [Plan(q) for q in self.problems]
+        self.plasma = [pl.alloc_plasma(device) for pl in self.plans]
+        self.draws = []
+        for q in self.problems:
+            d = inputs.plasma_draws(q)
+            self.draws.append(None if d is None else torch.from_numpy(d).to(device))
+        self.jb = [pl.alloc_jb(device) for pl in self.plans]
+        self.fields = [pl.alloc_fields(device) for pl in self.plans]
+        self.counters = Plan.alloc_counters(device)
+        ws = max(pl.sizes.workspace for pl in self.plans)
+        self.workspace = torch.zeros(ws, dtype=torch.uint8, device=device)
+        zero_counters(self.counters)
+        for pl, jb in zip(self.plans, self.jb):
+            pl.beam_current_analytic(jb)
+        self.batch = Batch(self.plans, device)
+        self.batch.describe(self.plasma, self.jb, self.fields, self.counters)
+        self.threads = 0
+        self.wg_per_cu = 0
+        self.graph = None
+
+    @property
+    def updates(self) -> int:
+        """Plasma particle-slice updates of one pass over every instance."""
+        return sum(q.updates_per_response() for q in self.problems)
+
+    def load(self, stream=None):
+        for pl, t, d in zip(self.plans, self.plasma, self.draws):
+            pl.init_plasma(t, d, stream)
+
+    def run(self, stream=None):
+        self.load(stream)
+        self.batch.response(stream, self.threads, self.wg_per_cu)
+
+    def run_one(self, i: int, stream=None):
+        pl = self.plans[i]
+        pl.init_plasma(self.plasma[i], self.draws[i], stream)
+        pl.plasma_response(self.plasma[i], self.jb[i], self.fields[i], self.workspace,
+                           self.counters, stream)
+
+    def capture(self):
+        """Record run() (plasma loads, queue reset, batched march) in a HIP
+        graph; replay() then submits the whole pass at once."""
+        import torch
+        self.run()                          # first use sets kernel attributes
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise WakeError("Scan.capture must be called first")
+        self.graph.replay()

@@ -1,0 +1,149 @@
+"""Batched parameter scan on the GPU: one persistent launch of many uneven
+fixed-beam instances, its launch shapes, the autotuner and HIP-graph replay,
+each checked against the FP64 oracle (or, for shape and replay variants,
+against the eager batched result) through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1411_3246_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1411_3246_amd import wake
+    wake.lib()
+    return wake
+
+
+def _np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+def _l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def small_scan(n=10, prec="fp64", seed=3):
+    """Scan instances with the scan's parameter ranges but grids the oracle
+    finishes in seconds (ragged n_r, n_xi and ppc; warm and cold)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        u_th = 0.0 if i % 4 == 0 else float(rng.uniform(0.0, 0.05))
+        out.append(inputs.facet_two_bunch(
+            n_r=int(rng.choice([16, 24, 40, 64])), n_xi=int(rng.integers(64, 300)),
+            ppc=int(rng.choice([2, 4, 6, 8])), u_th=u_th, sep=float(rng.uniform(3.0, 6.0)),
+            n_beam=0, n_steps=0, prec=prec, n_d=1.0, seed=seed * 1000 + i, name=f"small-scan-{i}"))
+    return out
+
+
+def _oracle(O, q):
+    return O.response(q, inputs.plasma_draws(q))
+
+
+@pytest.fixture(scope="module")
+def refs(O):
+    return [_oracle(O, q) for q in small_scan()]
+
+
+def test_scan_matches_oracle_every_shape(O, W, refs):
+    """Every launch shape the tuner may pick gives the oracle's fields."""
+    import torch
+    from paper_1411_3246_amd import autotune
+    scan = W.Scan(small_scan())
+    for threads, per_cu in autotune.CANDIDATES:
+        print(f"shape threads={threads} wg_per_cu={per_cu}", flush=True)
+        scan.threads, scan.wg_per_cu = threads, per_cu
+        for f in scan.fields:
+            f.zero_()
+        scan.run()
+        torch.cuda.synchronize()
+        for q, f, ref in zip(scan.problems, scan.fields, refs):
+            assert _rel(_np(f), ref["fields"]) <= 1e-9, (q.name, threads, per_cu)
+    c = W.counters_dict(scan.counters)
+    assert c["nonfinite"] == 0
+
+
+def test_scan_standalone_equals_batched(O, W, refs):
+    import torch
+    scan = W.Scan(small_scan())
+    for i in range(len(scan.problems)):
+        scan.run_one(i)
+    torch.cuda.synchronize()
+    for q, f, ref in zip(scan.problems, scan.fields, refs):
+        assert _rel(_np(f), ref["fields"]) <= 1e-9, q.name
+
+
+def test_autotuner_picks_a_valid_shape(O, W, refs):
+    import torch
+    from paper_1411_3246_amd import autotune
+    scan = W.Scan(small_scan())
+    best, table = autotune.tune_scan(scan)
+    assert best in autotune.CANDIDATES
+    assert len(table) == len(autotune.CANDIDATES) and all(r["ms"] > 0 for r in table)
+    scan.run()
+    torch.cuda.synchronize()
+    for q, f, ref in zip(scan.problems, scan.fields, refs):
+        assert _rel(_np(f), ref["fields"]) <= 1e-9, q.name
+
+
+def test_graph_replays_match_eager(O, W, refs):
+    """The whole pass (plasma loads, queue reset, batched march) captured in
+    a HIP graph: several replays, with eager work and synchronizations in
+    between, each equal to the oracle."""
+    import torch
+    scan = W.Scan(small_scan())
+    scan.capture()
+    other = W.Scan(small_scan(n=3, seed=11))
+    for rep in range(3):
+        print(f"graph replay {rep}", flush=True)
+        for f in scan.fields:
+            f.fill_(7.0)
+        scan.replay()
+        torch.cuda.synchronize()
+        for q, f, ref in zip(scan.problems, scan.fields, refs):
+            assert _rel(_np(f), ref["fields"]) <= 1e-9, (rep, q.name)
+        other.run()                           # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_full_scan_sampled_against_oracle(O, W):
+    """The 256-instance scan at its full sizes in mixed precision, launched as
+    the benchmark launches it; the smallest instances are recomputed by the
+    FP64 oracle one by one (E_z within 1e-3), all instances finite."""
+    import torch
+    probs = inputs.scan_instances(256)
+    scan = W.Scan(probs)
+    scan.run()
+    torch.cuda.synchronize()
+    c = W.counters_dict(scan.counters)
+    assert c["nonfinite"] == 0
+    order = sorted(range(len(probs)), key=lambda i: probs[i].updates_per_response())
+    for i in order[:3]:
+        q = probs[i]
+        print(f"sampled instance {q.name} {q.n_r}x{q.n_xi} ppc={q.ppc} u_th={q.u_th:.4f}", flush=True)
+        ref = _oracle(O, q.replace(prec="fp64"))
+        f = _np(scan.fields[i])
+        assert _l2(f[1], ref["fields"][1]) <= 1e-3, q.name
+        assert _l2(f[0], ref["fields"][0]) <= 1e-3, q.name
+    # the largest instance: properties that hold at any size
+    big = order[-1]
+    f = _np(scan.fields[big])
+    assert np.all(np.isfinite(f))
+    # first slice: the plasma is unperturbed, so psi, E_z and W vanish there
+    for k in (0, 1, 3):
+        assert np.max(np.abs(f[k, 0])) <= 1e-6 * max(np.max(np.abs(f[k])), 1e-30), k
