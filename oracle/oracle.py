@@ -256,3 +256,46 @@ def cycle(p, plasma_eps, beam_eps, n_steps: int, frozen_after_first: bool = Fals
     return {"beam": b, "gamma_init": g_init, "fields": fields, "counters": counters,
             "n_out_deposit": nout_dep, "n_out_push": nout_push,
             "witness_gain": mean_gain(b, g_init, 1) if len(p.bunches) > 1 else None}
+
+
+# ---------------------------------------------------------------------------
+# Differentiable objective and its finite-difference gradient
+# ---------------------------------------------------------------------------
+
+def objective(p, n_steps: Optional[int] = None) -> float:
+    """Witness mean gamma gain after one plasma response and n_steps beam
+    steps in its frozen fields (Section II A cycle with the fields held), for
+    the seeded draws of p."""
+    from paper_1411_3246_amd import inputs
+    n = p.n_steps if n_steps is None else n_steps
+    r = cycle(p, inputs.plasma_draws(p), inputs.beam_draws(p), n, frozen_after_first=True)
+    return r["witness_gain"]
+
+
+def fd_gradient(p, rel_h: float = 1e-4, n_steps: Optional[int] = None,
+                richardson: bool = True, which=None):
+    """Central finite differences of objective() in each theta component
+    (inputs.theta_of) with step rel_h |theta_i|; with richardson, the
+    estimates at h and h/2 are combined, (4 D(h/2) - D(h)) / 3, and the
+    difference between the two is returned as the truncation estimate."""
+    from paper_1411_3246_amd import inputs
+    th = inputs.theta_of(p)
+    g = np.zeros(len(th))
+    err = np.zeros(len(th))
+    for i in (range(len(th)) if which is None else which):
+        h = rel_h * abs(th[i])
+
+        def central(hh):
+            tp = th.copy(); tp[i] += hh
+            tm = th.copy(); tm[i] -= hh
+            return (objective(inputs.with_theta(p, tp), n_steps)
+                    - objective(inputs.with_theta(p, tm), n_steps)) / (2.0 * hh)
+
+        d1 = central(h)
+        if richardson:
+            d2 = central(0.5 * h)
+            g[i] = (4.0 * d2 - d1) / 3.0
+            err[i] = abs(d2 - d1)
+        else:
+            g[i] = d1
+    return g, err

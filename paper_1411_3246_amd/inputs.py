@@ -130,10 +130,11 @@ def blowout_response() -> Problem:
     return facet_two_bunch(name="two-bunch-512x4096-ppc16-beam1e6")
 
 
-def gradient_case() -> Problem:
-    """256 x 2048, 16 ppc, 2e5 beam particles, one response + 20 steps."""
-    return facet_two_bunch(n_r=256, n_xi=2048, ppc=16, n_beam=200_000, n_steps=20,
-                           name="two-bunch-256x2048-ppc16-beam2e5")
+def gradient_case(n_d: float = 8.0) -> Problem:
+    """256 x 2048, 16 ppc, 2e5 beam particles, one response + 20 steps in
+    its frozen fields, FP64 (the differentiable objective)."""
+    return facet_two_bunch(n_r=256, n_xi=2048, ppc=16, n_beam=200_000, n_steps=20, n_d=n_d,
+                           prec="fp64", name="two-bunch-256x2048-ppc16-beam2e5")
 
 
 def convergence_cyl() -> Problem:
@@ -162,6 +163,31 @@ def scan_instances(n: int = 256, seed: int = 0, prec: str = "mixed") -> List[Pro
                                    n_beam=0, n_steps=0, prec=prec, seed=seed * 100003 + i,
                                    name=f"scan-{i}"))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Parameters of the differentiable objective
+# ---------------------------------------------------------------------------
+
+THETA_NAMES = ("n_drive", "sigma_r", "sigma_z_drive", "separation", "u_th")
+
+
+def theta_of(p: Problem) -> np.ndarray:
+    """theta = (drive peak density, common sigma_r, drive sigma_z, witness
+    separation behind the drive, thermal spread u_th) of a two-bunch problem.
+    The drive peak density carries the drive charge at fixed widths; the
+    witness keeps its own peak density and length."""
+    d, w = p.bunches[0], p.bunches[1]
+    return np.array([d.n_peak, p.sigma_r, d.sigma_z, w.xi_c - d.xi_c, p.u_th])
+
+
+def with_theta(p: Problem, theta) -> Problem:
+    """The problem p with the parameters theta (see theta_of); the random
+    draws of both loaders depend only on the seed, so they stay fixed."""
+    t = [float(v) for v in theta]
+    d, w = p.bunches[0], p.bunches[1]
+    return p.replace(sigma_r=t[1], u_th=t[4],
+                     bunches=[Bunch(t[0], t[2], d.xi_c), Bunch(w.n_peak, w.sigma_z, d.xi_c + t[3])])
 
 
 # ---------------------------------------------------------------------------
