@@ -271,6 +271,40 @@ wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t wh
 wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
                      double* d_out, void* stream);
 
+/* Gradient of the witness energy gain (reverse mode, FP64 plans with a
+ * two-bunch macroparticle beam).  The objective G is the charge-weighted mean
+ * gamma gain of the witness after one plasma response to the loaded beam and
+ * n_steps beam advances by dt in that response's frozen fields (Section II A:
+ * plasma response for the frozen beam, then the beam advanced over the long
+ * step).  Its parameters theta are, in this order: the drive peak density
+ * bunch[0].n_peak, the common sigma_r, the drive length bunch[0].sigma_z, the
+ * witness separation bunch[1].xi_c - bunch[0].xi_c, and the thermal spread
+ * u_th (Eq. (12) beam, thermal plasma loading); the random draws of both
+ * loaders are held fixed.  The u_th component is defined for warm plans
+ * (u_th > 0) and is 0 otherwise.
+ *
+ * wk_gradient_forward loads the beam and the plasma from the draws, computes
+ * the beam current, marches the plasma (storing d_fields as
+ * wk_plasma_response does) while recording what the reverse pass needs in
+ * the workspace: per slice and Heun stage the node rows psi, psi', E_z,
+ * B_theta, J_r, J_z, M1..M5, and the particle state every `every` slices
+ * (the reverse pass recomputes the states in between); then advances the
+ * beam n_steps times, recording each step, and writes G to d_out[0].
+ * wk_gradient_backward, called after it with the same buffers and
+ * workspace, writes d_grad[0..4] = d_gbar[0] * dG/dtheta.  The workspace has
+ * wk_gradient_workspace_size bytes (0: the plan or arguments are not
+ * supported; the reason is in wk_last_error()).  The reverse march runs in
+ * one workgroup and needs n_r <= 740 (LDS). */
+size_t wk_gradient_workspace_size(const wk_plan* plan, int32_t n_steps, int32_t every);
+wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
+                              const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,
+                              int32_t every, void* d_fields, double* d_out, void* d_workspace,
+                              size_t workspace_bytes, uint64_t* d_counters, void* stream);
+wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
+                               const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,
+                               int32_t every, const void* d_fields, const double* d_gbar, double* d_grad,
+                               void* d_workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -495,3 +495,156 @@ wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Gradient of the witness gain (forward with recording, reverse pass)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GradLayout {
+    size_t plan_ws, jb, tape, ckpt, hist, fbar, jbbar, scratch, ybar, d0bar, wbar, sb0, wbar_beam, wsum, partials;
+    size_t total;
+};
+
+wk_status grad_check(const wk_plan* pl, int32_t n_steps, int32_t every)
+{
+    if (!pl) return fail(WK_ERR_INVALID_ARG, "NULL plan");
+    if (pl->p.prec != WK_FP64) return fail(WK_ERR_UNSUPPORTED, "the gradient needs an FP64 plan");
+    if (pl->p.n_bunch != 2 || pl->p.n_beam <= 0)
+        return fail(WK_ERR_UNSUPPORTED, "the gradient needs a two-bunch beam of macroparticles");
+    if (n_steps < 0) return fail(WK_ERR_INVALID_ARG, "n_steps must be >= 0");
+    if (every < 1) return fail(WK_ERR_INVALID_ARG, "checkpoint interval must be >= 1");
+    if (wk::adjoint_lds_bytes(pl->N1) > 159 * 1024)
+        return fail(WK_ERR_UNSUPPORTED, "n_r = %d is too large for the reverse march (LDS)", pl->N);
+    return WK_OK;
+}
+
+GradLayout grad_layout(const wk_plan* pl, int32_t n_steps, int32_t every)
+{
+    GradLayout L;
+    const size_t d = sizeof(double);
+    const int64_t np = pl->np, nb = pl->p.n_beam;
+    const size_t nxn = (size_t)pl->p.n_xi * pl->N1;
+    const int64_t nck = (pl->p.n_xi - 1) / every + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += a256(bytes);
+        return at;
+    };
+    L.plan_ws = take(pl->sizes.workspace);
+    L.jb = take(d * nxn);
+    L.tape = take(d * wk::adjoint_tape_doubles(pl->p.n_xi, pl->N1));
+    L.ckpt = take(d * (size_t)nck * 4 * np);
+    L.hist = take(d * (size_t)(n_steps + 1) * 6 * nb);
+    L.fbar = take(d * 4 * nxn);
+    L.jbbar = take(d * nxn);
+    L.scratch = take(d * wk::adjoint_scratch_doubles(np, every));
+    L.ybar = take(d * 4 * np);
+    L.d0bar = take(d * np);
+    L.wbar = take(d * np);
+    L.sb0 = take(d * 6 * nb);
+    L.wbar_beam = take(d * nb);
+    L.wsum = take(d);
+    L.partials = take(d * wk::theta_partials_doubles());
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wk_gradient_workspace_size(const wk_plan* plan, int32_t n_steps, int32_t every)
+{
+    if (grad_check(plan, n_steps, every) != WK_OK) return 0;
+    return grad_layout(plan, n_steps, every).total;
+}
+
+wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
+                              const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,
+                              int32_t every, void* d_fields, double* d_out, void* d_workspace, size_t workspace_bytes,
+                              uint64_t* d_counters, void* stream)
+{
+    wk_status st = grad_check(plan, n_steps, every);
+    if (st != WK_OK) return st;
+    if (!d_fields || !d_out || !d_workspace || !d_counters || !d_beam_draws)
+        return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (plan->p.u_th > 0.0 && !d_plasma_draws) return fail(WK_ERR_INVALID_ARG, "warm plasma needs draws");
+    if (!std::isfinite(dt)) return fail(WK_ERR_INVALID_ARG, "dt must be finite");
+    if ((st = check_plasma(plan, plasma)) != WK_OK) return st;
+    if ((st = check_beam(plan, beam)) != WK_OK) return st;
+    const GradLayout L = grad_layout(plan, n_steps, every);
+    if (workspace_bytes < L.total) return fail(WK_ERR_BUFFER, "gradient workspace needs %zu bytes", L.total);
+    char* ws = (char*)d_workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const wk::GridDesc g = grid_of(plan);
+    double* jb = (double*)(ws + L.jb);
+    hipError_t e = wk::launch_init_beam(g, plan->p, *beam, d_beam_draws, s);
+    if (e == hipSuccess)
+        e = wk::launch_beam_current(g, plan->p.n_beam, *beam, jb, ws + L.plan_ws + plan->ws_beam_off,
+                                    (unsigned long long*)d_counters, s);
+    if (e == hipSuccess)
+        e = wk::launch_init_plasma(g, plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec, *plasma, d_plasma_draws, s);
+    if (e != hipSuccess) return hip_status(e, "gradient forward (load)");
+    const wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
+    e = wk::launch_march_record(md, plan->shape.threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt), every, s);
+    if (e != hipSuccess) return hip_status(e, "gradient forward (march)");
+    e = wk::launch_push_record(g, plan->p.n_beam, *beam, (const double*)d_fields, n_steps, dt,
+                               (double*)(ws + L.hist), (unsigned long long*)d_counters, s);
+    const size_t gain_off = L.plan_ws + plan->ws_beam_off + wk::beam_ws_bytes(plan->p.n_xi, plan->p.n_beam) -
+                            a256(sizeof(double) * 2 * 512);
+    if (e == hipSuccess) e = wk::launch_mean_gain(plan->p.n_beam, *beam, 1, d_out, ws + gain_off, s);
+    return hip_status(e, "gradient forward (push)");
+}
+
+wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
+                               const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,
+                               int32_t every, const void* d_fields, const double* d_gbar, double* d_grad,
+                               void* d_workspace, size_t workspace_bytes, void* stream)
+{
+    wk_status st = grad_check(plan, n_steps, every);
+    if (st != WK_OK) return st;
+    if (!d_fields || !d_gbar || !d_grad || !d_workspace || !d_beam_draws)
+        return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (plan->p.u_th > 0.0 && !d_plasma_draws) return fail(WK_ERR_INVALID_ARG, "warm plasma needs draws");
+    if ((st = check_plasma(plan, plasma)) != WK_OK) return st;
+    if ((st = check_beam(plan, beam)) != WK_OK) return st;
+    const GradLayout L = grad_layout(plan, n_steps, every);
+    if (workspace_bytes < L.total) return fail(WK_ERR_BUFFER, "gradient workspace needs %zu bytes", L.total);
+    char* ws = (char*)d_workspace;
+    wk::GradDesc gd;
+    gd.march = make_desc(plan, plasma, nullptr, nullptr, nullptr);
+    gd.grid = grid_of(plan);
+    gd.beam = *beam;
+    gd.n_beam = plan->p.n_beam;
+    gd.n_drive = plan->p.n_drive;
+    gd.n_steps = n_steps;
+    gd.every = every;
+    gd.dt = dt;
+    gd.n_d = plan->p.bunch[0].n_peak;
+    gd.sigma_r = plan->p.sigma_r;
+    gd.sigma_zd = plan->p.bunch[0].sigma_z;
+    gd.u_th = plan->p.u_th;
+    gd.fields = (const double*)d_fields;
+    gd.tape = (const double*)(ws + L.tape);
+    gd.ckpt = (const double*)(ws + L.ckpt);
+    gd.hist = (const double*)(ws + L.hist);
+    gd.fbar = (double*)(ws + L.fbar);
+    gd.jbbar = (double*)(ws + L.jbbar);
+    gd.scratch = (double*)(ws + L.scratch);
+    gd.ybar = (double*)(ws + L.ybar);
+    gd.d0bar = (double*)(ws + L.d0bar);
+    gd.wbar = (double*)(ws + L.wbar);
+    gd.sb0 = (double*)(ws + L.sb0);
+    gd.wbar_beam = (double*)(ws + L.wbar_beam);
+    gd.wsum = (double*)(ws + L.wsum);
+    gd.partials = (double*)(ws + L.partials);
+    gd.beam_draws = d_beam_draws;
+    gd.plasma_draws = d_plasma_draws;
+    gd.gbar = d_gbar;
+    gd.grad = d_grad;
+    return hip_status(wk::launch_gradient_backward(gd, (hipStream_t)stream), "gradient backward");
+}
+
+}  // extern "C"

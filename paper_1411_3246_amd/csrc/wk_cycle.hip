@@ -103,7 +103,7 @@ __device__ __forceinline__ unsigned compact_append(const unsigned* old_order, un
 }
 
 template <typename R, class M>
-struct CycleHooks {
+struct CycleHooks : M::NoRecord {
     const CycleDescFull c;
     int n;                 // response index
     int next_bin;          // first bin not yet processed

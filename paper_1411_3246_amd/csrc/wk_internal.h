@@ -114,4 +114,43 @@ struct CycleDesc {
 size_t cycle_lds_bytes(int n_nodes);
 hipError_t launch_cycle(const CycleDesc& c, int prec, int threads, int grid, hipStream_t s);
 
+// Reverse-mode derivative of the witness gain (wk_adjoint.hip).
+struct GradDesc {
+    MarchDesc march;             // FP64 plasma of the forward (constants d0, w)
+    GridDesc grid;
+    wk_beam_bufs beam;
+    int64_t n_beam, n_drive;
+    int n_steps, every;
+    double dt;
+    double n_d, sigma_r, sigma_zd, u_th;     // the parameters
+    const double* fields;        // [4][n_xi][N1] of the forward
+    const double* tape;
+    const double* ckpt;
+    const double* hist;          // [n_steps + 1][6][n_beam]
+    double* fbar;                // [4][n_xi][N1]
+    double* jbbar;               // [n_xi][N1]
+    double* scratch;             // adjoint_scratch_doubles
+    double* ybar;                // [4][np]
+    double* d0bar;               // [np]
+    double* wbar;                // [np]
+    double* sb0;                 // [6][n_beam]
+    double* wbar_beam;           // [n_beam]
+    double* wsum;                // 1
+    double* partials;            // theta_partials_doubles
+    const double* beam_draws;
+    const double* plasma_draws;
+    const double* gbar;          // 1
+    double* grad;                // 5
+};
+size_t adjoint_lds_bytes(int n_nodes);
+int adjoint_threads();
+size_t adjoint_tape_doubles(int n_xi, int n_nodes);
+size_t adjoint_scratch_doubles(int64_t np, int every);
+size_t theta_partials_doubles();
+hipError_t launch_march_record(const MarchDesc& d, int threads, double* tape, double* ckpt, int every,
+                               hipStream_t s);
+hipError_t launch_push_record(const GridDesc& g, int64_t n, const wk_beam_bufs& b, const double* fields,
+                              int n_steps, double dt, double* hist, unsigned long long* counters, hipStream_t s);
+hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s);
+
 }  // namespace wk

@@ -604,8 +604,49 @@ struct Marcher {
         }
     }
 
+    // Hooks called with the field rows of each stage: before_b(k, stage) with
+    // psi, psi', E_z and the current/moment rows ready (B not yet solved),
+    // after_b(k, stage, B) with B_theta solved.  No-ops by default.
+    struct NoRecord {
+        __device__ __forceinline__ void before_b(Marcher&, int, int) {}
+        __device__ __forceinline__ void after_b(Marcher&, int, int, const double*) {}
+    };
+
+    // Run fn(i, part) over this thread's particles (read only), i the
+    // particle index.
+    template <typename Fn>
+    __device__ __forceinline__ void for_idx(Fn fn)
+    {
+        if (RESIDENT) {
+            const int64_t i0 = (int64_t)blk * K;
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                if (i0 + m < d.np) {
+                    Part<R> p;
+                    p.x = X[m];
+                    p.y = Y[m];
+                    p.px = PX[m];
+                    p.py = PY[m];
+                    p.d0 = cd0[m * T + tid];
+                    p.w = cw[m * T + tid];
+                    fn(i0 + m, p);
+                }
+            }
+        } else {
+            const int64_t per_tile = (int64_t)T * K;
+            for (int64_t base = 0; base < d.np; base += per_tile) {
+                const int64_t i0 = base + (int64_t)blk * K;
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    const int64_t i = i0 + m;
+                    if (i < d.np) fn(i, load(i));
+                }
+            }
+        }
+    }
+
     // Default hooks: beam current rows read from the descriptor's jb array.
-    struct GlobalJb {
+    struct GlobalJb : NoRecord {
         __device__ __forceinline__ void before_slice(Marcher&, int) {}
         __device__ __forceinline__ const double* jb_row(Marcher& m, int k) { return m.d.jb + (int64_t)k * m.N1; }
         __device__ __forceinline__ void after_store(Marcher&, int) {}
@@ -673,7 +714,9 @@ struct Marcher {
             __syncthreads();
             if (wid == 0) solve_ez(ez);
             __syncthreads();
+            hooks.before_b(*this, k, 0);
             solve_b(dpsi2, ez, b1);
+            hooks.after_b(*this, k, 0, b1);
             // keep the stage-1 psi, psi' for the derivative recomputed later
             __syncthreads();
             for (int j = tid; j < N1; j += T) {
@@ -709,7 +752,9 @@ struct Marcher {
             __syncthreads();
             if (wid == 0) solve_ez(ez);
             __syncthreads();
+            hooks.before_b(*this, k, 1);
             solve_b(dpsi2, ez, b2);
+            hooks.after_b(*this, k, 1, b2);
             __syncthreads();
             // ---- corrector Y_{k+1} = Y_k + dxi/2 (f_k + f*), deposit S(Y_{k+1}) ----
             {

@@ -68,11 +68,12 @@ EXPORTS = [
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle",
+    "wk_gradient_workspace_size", "wk_gradient_forward", "wk_gradient_backward",
 ]
 
 _NON_STATUS = {"wk_version", "wk_status_string", "wk_last_error", "wk_plan_destroy",
                "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size",
-               "wk_cycle_workspace_size"}
+               "wk_cycle_workspace_size", "wk_gradient_workspace_size"}
 
 _lib = None
 
@@ -112,6 +113,12 @@ def lib():
                                     C.POINTER(vp), vp, C.c_size_t, vp, vp]
     L.wk_batch_response.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, vp]
     L.wk_batch_response_shape.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, i32, i32, vp]
+    L.wk_gradient_workspace_size.argtypes = [vp, i32, i32]
+    L.wk_gradient_workspace_size.restype = C.c_size_t
+    L.wk_gradient_forward.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, C.POINTER(WkBeamBufs), vp, i32, d, i32,
+                                      vp, vp, vp, C.c_size_t, vp, vp]
+    L.wk_gradient_backward.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, C.POINTER(WkBeamBufs), vp, i32, d, i32,
+                                       vp, vp, vp, vp, C.c_size_t, vp]
     L.wk_beam_push.argtypes = [vp, C.POINTER(WkBeamBufs), vp, i32, d, vp, vp]
     L.wk_mean_gain.argtypes = [vp, C.POINTER(WkBeamBufs), i32, vp, vp, vp]
     L.wk_ez_peak.argtypes = [vp, vp, d, vp, vp]
@@ -500,3 +507,100 @@ class Scan:
         if self.graph is None:
             raise WakeError("Scan.capture must be called first")
         self.graph.replay()
+
+
+# ---------------------------------------------------------------------------
+# Differentiable objective: witness gain after one response + frozen pushes
+# ---------------------------------------------------------------------------
+
+class GradientRun:
+    """Buffers of one evaluation of the witness-gain objective and of its
+    reverse-mode gradient (wk_gradient_forward / wk_gradient_backward).
+    The problem must be FP64 with a two-bunch macroparticle beam."""
+
+    def __init__(self, problem: inputs.Problem, n_steps: Optional[int] = None, every: int = 64,
+                 device="cuda"):
+        import torch
+        self.problem = problem
+        self.n_steps = problem.n_steps if n_steps is None else int(n_steps)
+        self.every = int(every)
+        self.plan = Plan(problem)
+        self.device = device
+        self.plasma = self.plan.alloc_plasma(device)
+        self.beam = self.plan.alloc_beam(device)
+        self.fields = self.plan.alloc_fields(device)
+        self.counters = self.plan.alloc_counters(device)
+        pd = inputs.plasma_draws(problem)
+        self.plasma_draws = None if pd is None else torch.from_numpy(pd).to(device)
+        self.beam_draws = torch.from_numpy(inputs.beam_draws(problem)).to(device)
+        self.ws_bytes = lib().wk_gradient_workspace_size(self.plan.handle, self.n_steps, self.every)
+        if self.ws_bytes == 0:
+            raise WakeError("wk_gradient_workspace_size: " + lib().wk_last_error().decode())
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.out = torch.zeros(1, dtype=torch.float64, device=device)
+        self.grad = torch.zeros(5, dtype=torch.float64, device=device)
+        self.gbar = torch.ones(1, dtype=torch.float64, device=device)
+        zero_counters(self.counters)
+
+    def forward(self, stream=None):
+        """Objective G on the device (self.out[0])."""
+        pb = self.plan.plasma_bufs(self.plasma)
+        bb = self.plan.beam_bufs(self.beam)
+        _check(lib().wk_gradient_forward(self.plan.handle, C.byref(pb), _ptr(self.plasma_draws), C.byref(bb),
+                                         _ptr(self.beam_draws), self.n_steps, float(self.problem.dt),
+                                         self.every, _ptr(self.fields), _ptr(self.out), _ptr(self.workspace),
+                                         self.ws_bytes, _ptr(self.counters), _stream(stream)),
+               "wk_gradient_forward")
+        return self.out
+
+    def backward(self, gbar=None, stream=None):
+        """d_gbar * dG/dtheta on the device (self.grad), theta in the order of
+        inputs.THETA_NAMES."""
+        if gbar is not None:
+            self.gbar.copy_(gbar.reshape(1).to(self.gbar))
+        pb = self.plan.plasma_bufs(self.plasma)
+        bb = self.plan.beam_bufs(self.beam)
+        _check(lib().wk_gradient_backward(self.plan.handle, C.byref(pb), _ptr(self.plasma_draws), C.byref(bb),
+                                          _ptr(self.beam_draws), self.n_steps, float(self.problem.dt),
+                                          self.every, _ptr(self.fields), _ptr(self.gbar), _ptr(self.grad),
+                                          _ptr(self.workspace), self.ws_bytes, _stream(stream)),
+               "wk_gradient_backward")
+        return self.grad
+
+
+def _witness_gain_function():
+    import torch
+
+    class WitnessGain(torch.autograd.Function):
+        """G(theta): witness mean gamma gain after one plasma response and
+        n_steps beam steps in its frozen fields, theta = (drive peak density,
+        sigma_r, drive sigma_z, separation, u_th).  Forward and backward run
+        the library's recording march and its hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, theta, base, n_steps, every):
+            p = inputs.with_theta(base, theta.detach().cpu().tolist())
+            run = GradientRun(p, n_steps, every, device="cuda")
+            g = run.forward().clone()
+            ctx.run = run
+            ctx.theta_device = theta.device
+            return g.reshape(())
+
+        @staticmethod
+        def backward(ctx, gout):
+            grad = ctx.run.backward(gout.detach().reshape(1).to("cuda", torch.float64)).clone()
+            return grad.to(ctx.theta_device), None, None, None
+
+    return WitnessGain
+
+
+_WG = None
+
+
+def witness_gain(theta, base: inputs.Problem, n_steps: Optional[int] = None, every: int = 64):
+    """Differentiable witness gain (torch.autograd) of the two-bunch problem
+    `base` with its parameters replaced by theta."""
+    global _WG
+    if _WG is None:
+        _WG = _witness_gain_function()
+    return _WG.apply(theta, base, base.n_steps if n_steps is None else n_steps, every)

@@ -1,0 +1,108 @@
+"""Reverse-mode gradient of the witness gain on the GPU (recording FP64
+march, hand-written adjoint) against the FP64 oracle: the objective itself,
+and the gradient against the oracle's central finite differences (O9 of the
+method's test plan: fixed draws, step 1e-4 |theta_i|, Richardson-combined),
+within max(1e-4 |g_fd|, 3 x the finite-difference truncation estimate)."""
+import numpy as np
+import pytest
+
+from paper_1411_3246_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1411_3246_amd import wake
+    wake.lib()
+    return wake
+
+
+def _case(**kw):
+    base = dict(n_r=32, n_xi=256, ppc=4, u_th=0.005, n_beam=2000, n_steps=20, n_d=0.1, prec="fp64",
+                name="grad-small")
+    base.update(kw)
+    return inputs.facet_two_bunch(**base)
+
+
+def _gpu(W, p, every=64):
+    import torch
+    run = W.GradientRun(p, every=every)
+    g = float(run.forward().item())
+    grad = run.backward().cpu().numpy().copy()
+    torch.cuda.synchronize()
+    return g, grad, run
+
+
+def _compare(grad, fd, err, which=range(5)):
+    for i in which:
+        tol = max(1e-4 * abs(fd[i]), 3.0 * err[i], 1e-12)
+        print(f"  {inputs.THETA_NAMES[i]:>14s} adjoint {grad[i]: .10e} fd {fd[i]: .10e} "
+              f"|diff| {abs(grad[i] - fd[i]):.2e} tol {tol:.2e}", flush=True)
+    for i in which:
+        tol = max(1e-4 * abs(fd[i]), 3.0 * err[i], 1e-12)
+        assert abs(grad[i] - fd[i]) <= tol, (inputs.THETA_NAMES[i], grad[i], fd[i])
+
+
+def test_objective_matches_oracle(O, W):
+    p = _case()
+    print(f"case {p.name}", flush=True)
+    g, _, run = _gpu(W, p)
+    assert g == pytest.approx(O.objective(p), rel=1e-9, abs=1e-12)
+    c = W.counters_dict(run.counters)
+    assert c["nonfinite"] == 0 and c["wall"] == 0
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n_d=1.0, u_th=0.01), dict(geom="slab", r_max=8.0, u_th=0.005),
+                                dict(u_th=0.0, n_r=24, ppc=3)],
+                         ids=["weak-warm", "moderate", "slab", "cold"])
+def test_adjoint_matches_finite_differences(O, W, kw):
+    p = _case(**kw)
+    print(f"case {kw}", flush=True)
+    _, grad, _ = _gpu(W, p)
+    which = (0, 1, 2, 3, 4) if p.u_th > 0 else (0, 1, 2, 3)
+    fd, err = O.fd_gradient(p, which=which)
+    _compare(grad, fd, err, which)
+    if p.u_th == 0:
+        assert grad[4] == 0.0
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(W):
+    p = _case()
+    ref = None
+    for every in (1, 7, 64, 1000):
+        print(f"every {every}", flush=True)
+        _, grad, _ = _gpu(W, p, every=every)
+        if ref is None:
+            ref = grad
+        else:
+            assert np.max(np.abs(grad - ref) / np.maximum(np.abs(ref), 1e-30)) <= 1e-10, every
+
+
+def test_autograd_function(W):
+    import torch
+    p = _case()
+    theta = torch.tensor(inputs.theta_of(p), dtype=torch.float64, requires_grad=True)
+    g = W.witness_gain(theta, p)
+    (dg,) = torch.autograd.grad(3.0 * g, theta)
+    _, grad, _ = _gpu(W, p)
+    assert np.allclose(dg.numpy(), 3.0 * grad, rtol=1e-12, atol=0.0)
+
+
+def test_gradient_case_full_size_weak_driver(O, W):
+    """The 256 x 2048, 16 ppc, 2e5-particle, 20-step gradient workload (weak
+    driver, checkpoints every 64 slices): drive density, drive length and
+    separation derivatives against the oracle's finite differences."""
+    p = inputs.gradient_case(n_d=0.1).replace(u_th=0.005)
+    print(f"case {p.name} n_d=0.1", flush=True)
+    g, grad, run = _gpu(W, p, every=64)
+    assert g == pytest.approx(O.objective(p), rel=1e-9)
+    fd, err = O.fd_gradient(p, which=(0, 2, 3))
+    _compare(grad, fd, err, (0, 2, 3))
