@@ -76,6 +76,9 @@ def parse():
                     help="skip the batched 256-instance parameter scan")
     ap.add_argument("--scan-instances", type=int, default=256)
     ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the gradient (adjoint / forward time) measurement")
+    ap.add_argument("--grad-reps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -157,6 +160,61 @@ def scan_bench(args, log):
         "counters": counters,
         "recipe": "u_th~U[0,0.05], sep~U[3,6], n_r in {128,256,512,1024}, n_xi~U{1024..4096}, "
                   "ppc in {8..32 even}, fixed analytic two-bunch beam, mixed precision",
+    }
+
+
+def grad_bench(args):
+    """Gradient of the witness gain on the 256 x 2048, 16 ppc, 2e5-particle,
+    20-step workload (blowout driver n_d = 8, u_th = 0.02, FP64, checkpoints
+    every 64 slices): time of the plain forward (beam load + current +
+    response + 20 pushes + gain), of the recording forward and of the reverse
+    pass, each the best of a few runs timed with HIP events."""
+    import torch
+    from paper_1411_3246_amd import inputs, wake
+    p = inputs.gradient_case()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        best = float("inf")
+        fn()
+        torch.cuda.synchronize()
+        for _ in range(args.grad_reps):
+            ev[0].record(stream)
+            fn()
+            ev[1].record(stream)
+            ev[1].synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        return best
+
+    sim = wake.Simulation(p)
+
+    def plain():
+        sim.load_beam()
+        sim.beam_current()
+        sim.response()
+        sim.push(p.n_steps)
+        sim.plan.mean_gain(sim.beam, 1, sim.out[0:1], sim.workspace)
+
+    fwd = timed(plain)
+    g_plain = float(sim.out[0].item())
+    del sim
+    run = wake.GradientRun(p, every=64)
+    rec = timed(run.forward)
+    g = float(run.out[0].item())
+    bwd = timed(run.backward)
+    grad = run.grad.cpu().tolist()
+    counters = wake.counters_dict(run.counters)
+    del run
+    torch.cuda.empty_cache()
+    return {
+        "workload": p.name, "n_d": p.bunches[0].n_peak, "u_th": p.u_th, "n_steps": p.n_steps,
+        "checkpoint_every": 64, "precision": "fp64",
+        "forward_ms": fwd, "recording_forward_ms": rec, "backward_ms": bwd,
+        "adjoint_over_forward": bwd / fwd, "gradient_over_forward": (rec + bwd) / fwd,
+        "objective": g, "objective_plain": g_plain,
+        "gradient": dict(zip(inputs.THETA_NAMES, grad)),
+        "counters": counters,
     }
 
 
@@ -260,6 +318,10 @@ def main():
         sc = scan_bench(args, lambda row: print(f"# tuner {row}", file=sys.stderr, flush=True))
         line["batched_scan"] = sc
         line["batched_speedup"] = sc["batched_speedup"]
+    if not args.no_grad:
+        gr = grad_bench(args)
+        line["gradient"] = gr
+        line["adjoint_over_forward"] = gr["adjoint_over_forward"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -80,7 +80,7 @@ wk::GridDesc grid_of(const wk_plan* pl)
 int default_threads(int64_t np)
 {
     if (np <= 2048) return 256;
-    if (np <= 4096) return 512;
+    if (np <= 8192) return 512;
     return 1024;
 }
 
@@ -364,7 +364,7 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
     if (threads == 0) threads = plan_threads;
     // the resident variant (decided per instance in the kernel) when some
     // instance fits the registers; the launcher drops it if LDS cannot hold it
-    const bool resident = min_np <= (int64_t)threads * wk::march_tile();
+    const bool resident = min_np <= (int64_t)threads * wk::march_tile(threads);
     const size_t lds = wk::march_lds_bytes(max_nodes, threads);
     // workgroups resident per CU: bounded by LDS (160 KB) and by 2048 threads
     const int fit = (int)std::max<size_t>(1, std::min<size_t>((160 * 1024) / std::max<size_t>(lds, 1),

@@ -370,10 +370,15 @@ __global__ __launch_bounds__(T) void k_cycle(CycleDescFull c)
     }
 }
 
+// Particles per thread of the resident variant: up to 8192 particles stay in
+// registers at every workgroup size.
+template <int T>
+constexpr int cycle_tile() { return T >= 1024 ? 8 : 16; }
+
 template <typename R, int GEOM, bool WARM, int T>
 hipError_t launch_t(const CycleDescFull& c, int grid, hipStream_t s)
 {
-    constexpr int K = 8;
+    constexpr int K = cycle_tile<T>();
     const size_t lds = march_lds_bytes(c.base.n_r + 1, T) + (size_t)kRing * lds_stride(c.base.n_r + 1) * sizeof(double);
     const size_t lds_res = lds + 2 * (size_t)T * K * sizeof(R);
     const bool res = c.base.np <= (int64_t)T * K && lds_res + 1024 <= 160 * 1024;

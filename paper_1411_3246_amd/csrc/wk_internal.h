@@ -58,8 +58,8 @@ hipError_t launch_march(const MarchDesc& d, int prec, MarchShape shape, hipStrea
 hipError_t launch_march_batch(const MarchDesc* d_descs, int n, int max_nodes, int geom, int warm,
                               int prec, MarchShape shape, bool resident, int grid,
                               unsigned int* d_next, hipStream_t stream);
-// particles per thread per tile of the march kernel
-int march_tile();
+// particles per thread per tile of the march kernel at a workgroup size
+int march_tile(int threads);
 
 // Beam / loader kernels (wk_beam.hip)
 struct GridDesc {

@@ -59,13 +59,16 @@ __global__ __launch_bounds__(T) void k_march_batch(const MarchDesc* __restrict__
     }
 }
 
-constexpr int kK = 8;
+// Particles per thread: up to 8192 particles stay in registers at 512 and
+// 1024 threads per workgroup.
+constexpr int tile_for(int T) { return T >= 1024 ? 8 : 16; }
 constexpr size_t kMaxLds = 159 * 1024;  // leaves room for static LDS
 
 template <typename R, int GEOM, bool WARM, int T>
 hipError_t launch_one_t(const MarchDesc& d, hipStream_t s)
 {
     const size_t lds = march_lds_bytes(d.n_r + 1, T);
+    constexpr int kK = tile_for(T);
     const size_t lds_res = lds + 2 * (size_t)T * kK * sizeof(R);
     // the whole instance stays on chip when its D0 and w fit in LDS
     const bool res = d.np <= (int64_t)T * kK && lds_res <= kMaxLds;
@@ -88,6 +91,7 @@ hipError_t launch_batch_t(const MarchDesc* descs, int n, int max_nodes, bool res
                           hipStream_t s)
 {
     size_t lds = march_lds_bytes(max_nodes, T);
+    constexpr int kK = tile_for(T);
     if (res && lds + 2 * (size_t)T * kK * sizeof(R) > kMaxLds) res = false;
     if (res) lds += 2 * (size_t)T * kK * sizeof(R);
     if (res) {
@@ -146,7 +150,7 @@ hipError_t launch_batch_r(const MarchDesc* descs, int n, int max_nodes, int geom
 
 }  // namespace
 
-int march_tile() { return kK; }
+int march_tile(int threads) { return tile_for(threads); }
 
 hipError_t launch_march(const MarchDesc& d, int prec, MarchShape shape, hipStream_t stream)
 {
