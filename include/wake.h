@@ -293,8 +293,9 @@ wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
  * wk_gradient_backward, called after it with the same buffers and
  * workspace, writes d_grad[0..4] = d_gbar[0] * dG/dtheta.  The workspace has
  * wk_gradient_workspace_size bytes (0: the plan or arguments are not
- * supported; the reason is in wk_last_error()).  The reverse march runs in
- * one workgroup and needs n_r <= 740 (LDS). */
+ * supported; the reason is in wk_last_error()) and depends on the plan's
+ * workgroup size (wk_plan_set_threads), which the reverse march also uses.
+ * The reverse march runs in one workgroup and needs n_r <= 740 (LDS). */
 size_t wk_gradient_workspace_size(const wk_plan* plan, int32_t n_steps, int32_t every);
 wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
                               const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,

@@ -126,14 +126,7 @@ enum AdjRow {
 };
 constexpr int kSetRows = 7;   // per stage: psi, psi', E_z, B, M1, M2, M4
 
-// thread-major scratch arrays (each slots = kp * T doubles)
-enum AdjArr {
-    AR_SEG = 0,                 // every * 4 arrays: states of the segment
-};
-
-constexpr int kAdjT = 256;
-
-template <int GEOM, bool WARM>
+template <int GEOM, bool WARM, int kAdjT>
 struct Reverse {
     const AdjDesc& a;
     double* sm;
@@ -497,7 +490,9 @@ struct Reverse {
             wb[s] = 0.0;
             put(yb, s, adj::St{0.0, 0.0, 0.0, 0.0});
         }
-        for (int k = tid; k < nx * N1; k += kAdjT) a.jbbar[k] = 0.0;
+        // (same thread-to-node mapping as the accumulation in node_reverse)
+        for (int k = 0; k < nx; ++k)
+            for (int j = tid; j < N1; j += kAdjT) a.jbbar[(int64_t)k * N1 + j] = 0.0;
         const int nseg = (nx - 1) / a.every + 1;
         for (int sgi = nseg - 1; sgi >= 0; --sgi) {
             const int k0 = sgi * a.every;
@@ -614,11 +609,11 @@ struct Reverse {
     }
 };
 
-template <int GEOM, bool WARM>
-__global__ __launch_bounds__(kAdjT) void k_adjoint_march(AdjDesc a)
+template <int GEOM, bool WARM, int T>
+__global__ __launch_bounds__(T) void k_adjoint_march(AdjDesc a)
 {
     extern __shared__ double smem[];
-    Reverse<GEOM, WARM> r(a, smem);
+    Reverse<GEOM, WARM, T> r(a, smem);
     r.run();
 }
 
@@ -912,26 +907,35 @@ hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double
     }
 }
 
-template <int GEOM, bool WARM>
-hipError_t launch_reverse_t(const AdjDesc& a, hipStream_t s)
+template <int GEOM, bool WARM, int T>
+hipError_t launch_reverse_tt(const AdjDesc& a, hipStream_t s)
 {
     const size_t lds = (size_t)NUM_ADJ_ROWS * lds_stride(a.n_r + 1) * sizeof(double);
-    auto kern = k_adjoint_march<GEOM, WARM>;
+    auto kern = k_adjoint_march<GEOM, WARM, T>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(1), dim3(kAdjT), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(T), lds, s, a);
     return hipGetLastError();
+}
+
+template <int GEOM, bool WARM>
+hipError_t launch_reverse_t(const AdjDesc& a, int threads, hipStream_t s)
+{
+    switch (threads) {
+    case 256: return launch_reverse_tt<GEOM, WARM, 256>(a, s);
+    case 512: return launch_reverse_tt<GEOM, WARM, 512>(a, s);
+    default: return launch_reverse_tt<GEOM, WARM, 1024>(a, s);
+    }
 }
 
 }  // namespace
 
 size_t adjoint_lds_bytes(int n_nodes) { return (size_t)NUM_ADJ_ROWS * lds_stride(n_nodes) * sizeof(double); }
-int adjoint_threads() { return kAdjT; }
 size_t adjoint_tape_doubles(int n_xi, int n_nodes) { return (size_t)n_xi * 2 * kTapeRows * n_nodes; }
-size_t adjoint_scratch_doubles(int64_t np, int every)
+size_t adjoint_scratch_doubles(int64_t np, int every, int threads)
 {
-    const int64_t kp = (np + kAdjT - 1) / kAdjT;
-    const int64_t slots = kp * kAdjT;
+    const int64_t kp = (np + threads - 1) / threads;
+    const int64_t slots = kp * threads;
     return (size_t)((int64_t)every * 4 * slots + 16 * slots + 4 * slots);
 }
 
@@ -962,7 +966,7 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     a.n_xi = gd.grid.n_xi;
     a.every = gd.every;
     a.np = gd.march.np;
-    a.kp = (int)((a.np + kAdjT - 1) / kAdjT);
+    a.kp = (int)((a.np + gd.threads - 1) / gd.threads);
     a.r_max = gd.grid.r_max;
     a.h = gd.grid.h;
     a.dxi = gd.grid.dxi;
@@ -978,9 +982,11 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     a.d0bar_out = gd.d0bar;
     a.wbar_out = gd.wbar;
     if (gd.grid.geom == WK_CYL)
-        e = gd.march.warm ? launch_reverse_t<WK_CYL, true>(a, s) : launch_reverse_t<WK_CYL, false>(a, s);
+        e = gd.march.warm ? launch_reverse_t<WK_CYL, true>(a, gd.threads, s)
+                          : launch_reverse_t<WK_CYL, false>(a, gd.threads, s);
     else
-        e = gd.march.warm ? launch_reverse_t<WK_SLAB, true>(a, s) : launch_reverse_t<WK_SLAB, false>(a, s);
+        e = gd.march.warm ? launch_reverse_t<WK_SLAB, true>(a, gd.threads, s)
+                          : launch_reverse_t<WK_SLAB, false>(a, gd.threads, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_current_adjoint, dim3(blocks_for(nb, kBlk)), dim3(kBlk), 0, s, bg, nb, gd.beam, gd.hist,
                        gd.jbbar, gd.sb0, gd.wbar_beam);

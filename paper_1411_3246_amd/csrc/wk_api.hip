@@ -539,7 +539,7 @@ GradLayout grad_layout(const wk_plan* pl, int32_t n_steps, int32_t every)
     L.hist = take(d * (size_t)(n_steps + 1) * 6 * nb);
     L.fbar = take(d * 4 * nxn);
     L.jbbar = take(d * nxn);
-    L.scratch = take(d * wk::adjoint_scratch_doubles(np, every));
+    L.scratch = take(d * wk::adjoint_scratch_doubles(np, every, pl->shape.threads));
     L.ybar = take(d * 4 * np);
     L.d0bar = take(d * np);
     L.wbar = take(d * np);
@@ -621,6 +621,7 @@ wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma
     gd.n_drive = plan->p.n_drive;
     gd.n_steps = n_steps;
     gd.every = every;
+    gd.threads = plan->shape.threads;
     gd.dt = dt;
     gd.n_d = plan->p.bunch[0].n_peak;
     gd.sigma_r = plan->p.sigma_r;

@@ -120,7 +120,7 @@ struct GradDesc {
     GridDesc grid;
     wk_beam_bufs beam;
     int64_t n_beam, n_drive;
-    int n_steps, every;
+    int n_steps, every, threads;             // threads: workgroup size of the reverse march
     double dt;
     double n_d, sigma_r, sigma_zd, u_th;     // the parameters
     const double* fields;        // [4][n_xi][N1] of the forward
@@ -143,9 +143,8 @@ struct GradDesc {
     double* grad;                // 5
 };
 size_t adjoint_lds_bytes(int n_nodes);
-int adjoint_threads();
 size_t adjoint_tape_doubles(int n_xi, int n_nodes);
-size_t adjoint_scratch_doubles(int64_t np, int every);
+size_t adjoint_scratch_doubles(int64_t np, int every, int threads);
 size_t theta_partials_doubles();
 hipError_t launch_march_record(const MarchDesc& d, int threads, double* tape, double* ckpt, int every,
                                hipStream_t s);

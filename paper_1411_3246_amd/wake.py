@@ -519,12 +519,12 @@ class GradientRun:
     The problem must be FP64 with a two-bunch macroparticle beam."""
 
     def __init__(self, problem: inputs.Problem, n_steps: Optional[int] = None, every: int = 64,
-                 device="cuda"):
+                 device="cuda", threads: Optional[int] = None):
         import torch
         self.problem = problem
         self.n_steps = problem.n_steps if n_steps is None else int(n_steps)
         self.every = int(every)
-        self.plan = Plan(problem)
+        self.plan = Plan(problem, threads)
         self.device = device
         self.plasma = self.plan.alloc_plasma(device)
         self.beam = self.plan.alloc_beam(device)
