@@ -21,6 +21,7 @@ struct wk_plan {
     wk::MarchShape shape;
     wk_sizes sizes;
     size_t ws_fk_off, ws_beam_off;
+    bool big;   // node rows beyond LDS: the march keeps its field rows in the workspace
 };
 
 namespace {
@@ -135,6 +136,7 @@ wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double
     d.fields = fields;
     d.counters = (unsigned long long*)counters;
     d.cost = pl->np * (int64_t)pl->p.n_xi;
+    d.grow = nullptr;
     return d;
 }
 
@@ -190,7 +192,7 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
         if (!(p->gamma0 > 1.0)) return fail(WK_ERR_INVALID_ARG, "gamma0 must be > 1");
     }
     const int N1 = p->n_r + 1;
-    if (wk::march_lds_bytes(N1, 1024) > 160 * 1024)
+    if (wk::big_lds_bytes(N1) > 159 * 1024)
         return fail(WK_ERR_UNSUPPORTED, "n_r = %d needs more LDS than one workgroup has", p->n_r);
 
     wk_plan* pl = new (std::nothrow) wk_plan;
@@ -218,7 +220,9 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
     s.beam_tag = a256(sizeof(int32_t) * nb);
     s.beam_draws = a256(sizeof(double) * 4 * nb);
     pl->ws_fk_off = 0;
-    pl->ws_beam_off = 0;
+    // large grids: global node rows of the march first
+    pl->big = wk::march_needs_global_rows(N1);
+    pl->ws_beam_off = pl->big ? a256(wk::big_rows_bytes(N1)) : 0;
     s.workspace = pl->ws_beam_off + a256(wk::beam_ws_bytes(p->n_xi, p->n_beam));
     s.counters = a256(sizeof(uint64_t) * WK_NCOUNTERS);
     *out = pl;
@@ -298,7 +302,8 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
     wk_status st = check_plasma(plan, plasma);
     if (st != WK_OK) return st;
-    const wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, d_counters);
+    wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, d_counters);
+    if (plan->big) d.grow = (double*)d_workspace;
     return hip_status(wk::launch_march(d, plan->p.prec, plan->shape, (hipStream_t)stream), "plasma response");
 }
 
@@ -329,6 +334,7 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_p
             return fail(WK_ERR_UNSUPPORTED, "batch instances must share geometry and precision");
         wk_status st = check_plasma(pl, &h_plasma[i]);
         if (st != WK_OK) return st;
+        if (pl->big) return fail(WK_ERR_UNSUPPORTED, "instance %d: n_r = %d is too large for a batch", i, pl->N);
         if (!h_jb[i] || !h_fields[i]) return fail(WK_ERR_INVALID_ARG, "NULL jb or fields for instance %d", i);
         descs[i] = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], d_counters);
     }

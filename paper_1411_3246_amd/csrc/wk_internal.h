@@ -30,6 +30,7 @@ struct MarchDesc {
     void* fields;        // real[4][n_xi][n_r+1]
     unsigned long long* counters;
     int64_t cost;        // np * n_xi (scheduling weight)
+    double* grow;        // large grids: global node rows (BIG_ROWS x stride doubles)
 };
 
 // LDS rows used by the march kernel (each of `stride` doubles): the deposit
@@ -43,6 +44,12 @@ enum MarchRow {
 };
 
 __host__ __device__ inline int lds_stride(int n_nodes) { return (n_nodes + 1) & ~1; }
+// Large grids keep the deposit rows ROW_S..ROW_M5 in LDS and the others in
+// global memory.
+constexpr int BIG_LDS_ROWS = ROW_PSI1;
+constexpr int BIG_ROWS = NUM_ROWS - ROW_PSI1;
+inline size_t big_lds_bytes(int n_nodes) { return (size_t)BIG_LDS_ROWS * lds_stride(n_nodes) * sizeof(double); }
+inline size_t big_rows_bytes(int n_nodes) { return (size_t)BIG_ROWS * lds_stride(n_nodes) * sizeof(double); }
 inline size_t march_lds_bytes(int n_nodes, int /*threads*/)
 {
     return (size_t)NUM_ROWS * lds_stride(n_nodes) * sizeof(double);
@@ -60,6 +67,8 @@ hipError_t launch_march_batch(const MarchDesc* d_descs, int n, int max_nodes, in
                               unsigned int* d_next, hipStream_t stream);
 // particles per thread per tile of the march kernel at a workgroup size
 int march_tile(int threads);
+// true when the node rows of a grid exceed LDS (large-grid variant)
+bool march_needs_global_rows(int n_nodes);
 
 // Beam / loader kernels (wk_beam.hip)
 struct GridDesc {

@@ -24,11 +24,11 @@ namespace {
 
 using dev::Marcher;
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES>
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = false>
 __global__ __launch_bounds__(T) void k_march_one(MarchDesc d)
 {
     extern __shared__ double smem[];
-    Marcher<R, GEOM, WARM, K, RES> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+    Marcher<R, GEOM, WARM, K, RES, BIG> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
     m.run();
 }
 
@@ -64,9 +64,24 @@ __global__ __launch_bounds__(T) void k_march_batch(const MarchDesc* __restrict__
 constexpr int tile_for(int T) { return T >= 1024 ? 8 : 16; }
 constexpr size_t kMaxLds = 159 * 1024;  // leaves room for static LDS
 
+// Large grid (node rows beyond LDS): 1024 threads, particles streamed, the
+// field and solver rows in the descriptor's global rows.
+template <typename R, int GEOM, bool WARM>
+hipError_t launch_big(const MarchDesc& d, hipStream_t s)
+{
+    if (!d.grow) return hipErrorInvalidValue;
+    const size_t lds = big_lds_bytes(d.n_r + 1);
+    auto kern = k_march_one<R, GEOM, WARM, 1024, tile_for(1024), false, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(1024), lds, s, d);
+    return hipGetLastError();
+}
+
 template <typename R, int GEOM, bool WARM, int T>
 hipError_t launch_one_t(const MarchDesc& d, hipStream_t s)
 {
+    if (march_lds_bytes(d.n_r + 1, T) > kMaxLds) return launch_big<R, GEOM, WARM>(d, s);
     const size_t lds = march_lds_bytes(d.n_r + 1, T);
     constexpr int kK = tile_for(T);
     const size_t lds_res = lds + 2 * (size_t)T * kK * sizeof(R);
@@ -151,6 +166,7 @@ hipError_t launch_batch_r(const MarchDesc* descs, int n, int max_nodes, int geom
 }  // namespace
 
 int march_tile(int threads) { return tile_for(threads); }
+bool march_needs_global_rows(int n_nodes) { return march_lds_bytes(n_nodes, 0) > kMaxLds; }
 
 hipError_t launch_march(const MarchDesc& d, int prec, MarchShape shape, hipStream_t stream)
 {

@@ -75,9 +75,19 @@ __device__ __forceinline__ double wave_scan_rounds(int n, int lane, const G& g, 
     return carry;
 }
 
+// Store wait of the large-grid variant: its node rows partly live in global
+// memory, so a barrier must also wait for this thread's stores.
+template <bool GLOBAL_ROWS>
+__device__ __forceinline__ void block_sync()
+{
+    if (GLOBAL_ROWS) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
 // Parallel cyclic reduction by the whole workgroup of the tridiagonal system
 // with rows (a, b, c, d) in buffer 0 (a[0] and c[n-1] ignored); buffer 1 is
 // scratch.  Solution in x.  One barrier per reduction step.
+template <bool GLOBAL_ROWS = false>
 __device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, double* d0, double* a1, double* b1,
                           double* c1, double* d1, double* x, int n)
 {
@@ -102,7 +112,7 @@ __device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, do
             c1[i] = nc;
             d1[i] = nd;
         }
-        __syncthreads();
+        block_sync<GLOBAL_ROWS>();
         double* t;
         t = a0; a0 = a1; a1 = t;
         t = b0; b0 = b1; b1 = t;
@@ -206,7 +216,11 @@ struct Acc {
     }
 };
 
-template <typename R, int GEOM, bool WARM, int K, bool RESIDENT>
+// BIG: the large-grid variant.  Only the deposit rows (S, J_r, J_z, M1..M5)
+// are in LDS; the field, ion and solver rows are in the descriptor's
+// per-workgroup global rows (d.grow), and every barrier first waits for the
+// thread's stores.
+template <typename R, int GEOM, bool WARM, int K, bool RESIDENT, bool BIG = false>
 struct Marcher {
     const MarchDesc d;
     double* sm;
@@ -240,7 +254,16 @@ struct Marcher {
         dminR = (R)d.d_min;
     }
 
-    __device__ __forceinline__ double* row(int r) const { return sm + r * st; }
+    __device__ __forceinline__ double* row(int r) const
+    {
+        return (BIG && r >= ROW_PSI1) ? d.grow + (int64_t)(r - ROW_PSI1) * st : sm + r * st;
+    }
+    __device__ __forceinline__ void sync() const { block_sync<BIG>(); }
+    __device__ __forceinline__ void wsync() const
+    {
+        if (BIG) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        ::wk::dev::wave_sync();
+    }
 
     __device__ __forceinline__ Part<R> load(int64_t i) const
     {
@@ -438,12 +461,12 @@ struct Marcher {
                 const double irph = GEOM == WK_CYL ? rcp64(((double)j + 0.5) * h) : 1.0;
                 psi[j] = -h * incl * irph;
             });
-        wave_sync();
+        wsync();
         const double utot = wave_scan_rounds(
             N, lane, [&](int j) { return psi[j]; }, [&](int j, double excl, double) { psi[j] = excl; });
-        wave_sync();
+        wsync();
         for (int j = lane; j < N1; j += 64) psi[j] = j < N ? utot - psi[j] : 0.0;
-        wave_sync();
+        wsync();
         const double ih = rcp64(h);
         for (int j = lane; j < N1; j += 64) {
             double v;
@@ -471,7 +494,7 @@ struct Marcher {
         const double tot = wave_scan_rounds(
             N, lane, [&](int j) { return -(0.5 * h * (jr[j] + jr[j + 1])); },
             [&](int j, double excl, double) { ez[j] = excl; });
-        wave_sync();
+        wsync();
         for (int j = lane; j < N1; j += 64) ez[j] = j < N ? tot - ez[j] : 0.0;
     }
 
@@ -515,10 +538,10 @@ struct Marcher {
                 D[i] = 0.5 * (jz[N] + jz[N - 1]);
             }
         }
-        __syncthreads();
-        block_pcr(A, B, C, D, row(ROW_M2), row(ROW_M3), row(ROW_M4), row(ROW_M5), bt + 1, N);
+        sync();
+        block_pcr<BIG>(A, B, C, D, row(ROW_M2), row(ROW_M3), row(ROW_M4), row(ROW_M5), bt + 1, N);
         if (tid == 0) bt[0] = 0.0;
-        __syncthreads();
+        sync();
         for (int j = tid; j < N1; j += T)
             for (int r = ROW_S; r <= ROW_M5; ++r) row(r)[j] = 0.0;
     }
@@ -689,7 +712,7 @@ struct Marcher {
                 cw[m * T + tid] = p.w;
             }
         }
-        __syncthreads();
+        sync();
         {
             Acc<R, 1> a;
             a.reset(-1);
@@ -700,25 +723,25 @@ struct Marcher {
             hooks.before_slice(*this, k);
             const double* jb0 = hooks.jb_row(*this, k);
             // ---- stage 1 at (Y_k, xi_k): psi -> moments -> E_z, B ----
-            __syncthreads();
+            sync();
             if (wid == 0) solve_psi(psi2, dpsi2);
-            __syncthreads();
+            sync();
             {
                 Acc<R, 7> a;
                 a.reset(-1);
                 for_parts<false>([&](Part<R>& p) { dep_moments(a, p); });
                 flush_moments(a);
             }
-            __syncthreads();
+            sync();
             finalize_moments(jb0);
-            __syncthreads();
+            sync();
             if (wid == 0) solve_ez(ez);
-            __syncthreads();
+            sync();
             hooks.before_b(*this, k, 0);
             solve_b(dpsi2, ez, b1);
             hooks.after_b(*this, k, 0, b1);
             // keep the stage-1 psi, psi' for the derivative recomputed later
-            __syncthreads();
+            sync();
             for (int j = tid; j < N1; j += T) {
                 psi1[j] = psi2[j];
                 dpsi1[j] = dpsi2[j];
@@ -726,7 +749,7 @@ struct Marcher {
             store_fields(k, psi2, ez, b1, dpsi2);
             hooks.after_store(*this, k);
             if (k == d.n_xi - 1) break;
-            __syncthreads();
+            sync();
             // ---- stage 2 at (Y*, xi_{k+1}), Y* = Y_k + dxi f_k ----
             {
                 Acc<R, 1> a;
@@ -736,9 +759,9 @@ struct Marcher {
                 });
                 a.flush(row(ROW_S), st);
             }
-            __syncthreads();
+            sync();
             if (wid == 0) solve_psi(psi2, dpsi2);
-            __syncthreads();
+            sync();
             {
                 Acc<R, 7> a;
                 a.reset(-1);
@@ -747,15 +770,15 @@ struct Marcher {
                 });
                 flush_moments(a);
             }
-            __syncthreads();
+            sync();
             finalize_moments(hooks.jb_row(*this, k + 1));
-            __syncthreads();
+            sync();
             if (wid == 0) solve_ez(ez);
-            __syncthreads();
+            sync();
             hooks.before_b(*this, k, 1);
             solve_b(dpsi2, ez, b2);
             hooks.after_b(*this, k, 1, b2);
-            __syncthreads();
+            sync();
             // ---- corrector Y_{k+1} = Y_k + dxi/2 (f_k + f*), deposit S(Y_{k+1}) ----
             {
                 Acc<R, 1> a;

@@ -320,3 +320,23 @@ def test_pipelined_cycle_mixed_blowout(O, W):
     assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0 and c["nonfinite"] == 0
     ref = O.cycle(p.replace(prec="fp64"), inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
     assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-3)
+
+
+@pytest.mark.parametrize("geom", ["cyl", "slab"])
+def test_large_grid_rows_in_global_memory(O, W, geom):
+    """Grids whose node rows exceed LDS (here 1200 cells) keep only the
+    deposit rows in LDS and the field and solver rows in global memory:
+    FP64 parity with the oracle on a short window."""
+    p = inputs.facet_two_bunch(n_r=1200, n_xi=40, ppc=2, u_th=0.02, n_beam=0, prec="fp64", n_d=1.0,
+                               geom=geom, r_max=6.0 if geom == "cyl" else 8.0, name=f"large-{geom}")
+    _check_fp64(O, W, p, tol=1e-9)
+
+
+def test_large_grid_mixed(O, W):
+    p = inputs.facet_two_bunch(n_r=1400, n_xi=64, ppc=4, u_th=0.02, n_beam=0, prec="mixed", name="large-mixed")
+    print(f"case {p.name}", flush=True)
+    ref = oracle_response(O, p.replace(prec="fp64"))
+    sim = gpu_response(W, p, jb=ref["jb"])
+    f = _np(sim.fields)
+    assert _l2(f[1], ref["fields"][1]) <= 1e-3
+    assert _l2(f[0], ref["fields"][0]) <= 1e-3
