@@ -398,7 +398,7 @@ namespace {
 
 struct CycleLayout {
     int grid;
-    size_t count, start, fill, order, progress, ticket, plasma, total;
+    size_t count, start, fill, order, progress, ticket, plasma, big, total;
 };
 
 CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
@@ -406,8 +406,10 @@ CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
     CycleLayout L;
     const int nb = pl->p.n_xi + 1;
     const size_t lds = wk::cycle_lds_bytes(pl->N1);
+    const size_t big = wk::cycle_big_rows_bytes(pl->N1);
+    const int threads = big ? 1024 : pl->shape.threads;
     const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
-    L.grid = std::min(n_steps + 1, device_cus() * std::min(per_cu, 2048 / pl->shape.threads));
+    L.grid = std::min(n_steps + 1, device_cus() * std::min(per_cu, 2048 / threads));
     size_t o = 0;
     L.count = o; o += a256(sizeof(unsigned) * nb);
     L.start = o; o += a256(sizeof(unsigned) * 2 * (nb + 1));
@@ -416,6 +418,7 @@ CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
     L.progress = o; o += a256(sizeof(unsigned) * (size_t)std::max(n_steps, 1));
     L.ticket = o; o += 256;
     L.plasma = o; o += a256(sizeof(double) * 4 * (size_t)pl->np * (size_t)L.grid);
+    L.big = o; o += a256(big * (size_t)L.grid);
     L.total = o;
     return L;
 }
@@ -438,7 +441,7 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
     if (st != WK_OK) return st;
     st = check_beam(plan, beam);
     if (st != WK_OK) return st;
-    if (wk::cycle_lds_bytes(plan->N1) > 160 * 1024)
+    if (wk::cycle_lds_bytes(plan->N1) > 159 * 1024)
         return fail(WK_ERR_UNSUPPORTED, "n_r = %d is too large for the pipelined cycle", plan->N);
     const CycleLayout L = cycle_layout(plan, n_steps);
     if (workspace_bytes < L.total) return fail(WK_ERR_BUFFER, "cycle workspace needs %zu bytes", L.total);
@@ -461,11 +464,13 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
     c.ticket = (unsigned*)(ws + L.ticket);
     c.abort_flag = (unsigned long long*)(d_counters + WK_CNT_PIPELINE_ABORT);
     c.plasma_ws = (double*)(ws + L.plasma);
+    c.big_rows = wk::cycle_big_rows_bytes(plan->N1) ? (double*)(ws + L.big) : nullptr;
     c.ring = d_ring;
     c.slot_elems = (int64_t)4 * plan->p.n_xi * plan->N1;
     c.n_steps = n_steps;
     c.dt = dt;
-    return hip_status(wk::launch_cycle(c, plan->p.prec, plan->shape.threads, L.grid, s), "cycle");
+    const int threads = c.big_rows ? 1024 : plan->shape.threads;
+    return hip_status(wk::launch_cycle(c, plan->p.prec, threads, L.grid, s), "cycle");
 }
 
 wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields, int32_t n_steps,

@@ -24,7 +24,13 @@ namespace {
 
 using dev::Marcher;
 
-constexpr int kRing = 4;          // LDS rows of beam current in flight
+constexpr int kRing = 4;          // rows of beam current in flight
+
+// true when the node rows and the beam rows exceed LDS (large-grid variant)
+__host__ __device__ inline bool cycle_needs_global_rows(int n_nodes)
+{
+    return (size_t)(NUM_ROWS + kRing) * lds_stride(n_nodes) * sizeof(double) > 159 * 1024;
+}
 constexpr int kLag = 3;           // slices of response n-1 needed beyond a bin
 constexpr int kPublish = 4;       // slices between progress publications
 constexpr unsigned kSpinLimit = 1u << 26;
@@ -39,6 +45,7 @@ struct CycleDescFull {
     unsigned int* ticket;
     unsigned long long* abort_flag;
     double* plasma_ws;               // per workgroup: x, y, px, py (4 * np doubles)
+    double* big_rows;                // large grids, per workgroup: BIG_ROWS node rows + kRing beam rows
     void* ring;                      // 2 field slots, each 4 * n_xi * (n_r + 1) reals
     int64_t slot_elems;
     int64_t n_beam;
@@ -210,12 +217,17 @@ struct CycleHooks : M::NoRecord {
                 atomicAdd(r1 + j + 1, wb * tr * tk);
             }
         }
+        if (M::kBig) wait_stores();
         __syncthreads();
+        // large grids: the ring rows are in global memory and the deposits
+        // were L2 atomics, so drop this CU's L1 copies before reading them
+        if (M::kBig) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (n > 0) emit_stayers(b);
         // row b is complete: J_bz = -sum / (V_j dxi)
         double* rb = jb_ring(b);
         for (int j = threadIdx.x; j <= g.n_r; j += blockDim.x)
             rb[j] = -rb[j] / (dev::grid_node_volume(g, j) * g.dxi);
+        if (M::kBig) wait_stores();
         __syncthreads();
     }
 
@@ -291,16 +303,17 @@ __device__ __forceinline__ void push_bin_only(const CycleDescFull& c, const unsi
     }
 }
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES>
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = false>
 __global__ __launch_bounds__(T) void k_cycle(CycleDescFull c)
 {
     extern __shared__ double smem[];
     __shared__ int s_n;
     __shared__ int wtot[T / 64];
-    using M = Marcher<R, GEOM, WARM, K, RES>;
+    using M = Marcher<R, GEOM, WARM, K, RES, BIG>;
     const int N1 = c.base.n_r + 1;
     const int st = lds_stride(N1);
-    double* jb_rows = smem + NUM_ROWS * st;
+    double* grow = BIG ? c.big_rows + (int64_t)blockIdx.x * (BIG_ROWS + kRing) * st : nullptr;
+    double* jb_rows = BIG ? grow + (int64_t)BIG_ROWS * st : smem + NUM_ROWS * st;
     const int64_t np = c.base.np;
     double* mine = c.plasma_ws + (int64_t)blockIdx.x * 4 * np;
     for (;;) {
@@ -319,6 +332,7 @@ __global__ __launch_bounds__(T) void k_cycle(CycleDescFull c)
             d.px = mine + 2 * np;
             d.py = mine + 3 * np;
             d.fields = (R*)c.ring + (int64_t)(n & 1) * c.slot_elems;
+            d.grow = grow;
             for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
                 d.x[i] = c.base.x[i];
                 d.px[i] = c.base.px[i];
@@ -375,9 +389,24 @@ __global__ __launch_bounds__(T) void k_cycle(CycleDescFull c)
 template <int T>
 constexpr int cycle_tile() { return T >= 1024 ? 8 : 16; }
 
+// Large grids: 1024 threads, particles streamed, node rows and beam rows in
+// global memory.
+template <typename R, int GEOM, bool WARM>
+hipError_t launch_big(const CycleDescFull& c, int grid, hipStream_t s)
+{
+    if (!c.big_rows) return hipErrorInvalidValue;
+    const size_t lds = big_lds_bytes(c.base.n_r + 1);
+    auto kern = k_cycle<R, GEOM, WARM, 1024, cycle_tile<1024>(), false, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, s, c);
+    return hipGetLastError();
+}
+
 template <typename R, int GEOM, bool WARM, int T>
 hipError_t launch_t(const CycleDescFull& c, int grid, hipStream_t s)
 {
+    if (cycle_needs_global_rows(c.base.n_r + 1)) return launch_big<R, GEOM, WARM>(c, grid, s);
     constexpr int K = cycle_tile<T>();
     const size_t lds = march_lds_bytes(c.base.n_r + 1, T) + (size_t)kRing * lds_stride(c.base.n_r + 1) * sizeof(double);
     const size_t lds_res = lds + 2 * (size_t)T * K * sizeof(R);
@@ -416,7 +445,15 @@ hipError_t launch_r(const CycleDescFull& c, int threads, int grid, hipStream_t s
 
 }  // namespace
 
-size_t cycle_lds_bytes(int n_nodes) { return march_lds_bytes(n_nodes, 0) + (size_t)kRing * lds_stride(n_nodes) * sizeof(double); }
+size_t cycle_lds_bytes(int n_nodes)
+{
+    if (cycle_needs_global_rows(n_nodes)) return big_lds_bytes(n_nodes);
+    return march_lds_bytes(n_nodes, 0) + (size_t)kRing * lds_stride(n_nodes) * sizeof(double);
+}
+size_t cycle_big_rows_bytes(int n_nodes)
+{
+    return cycle_needs_global_rows(n_nodes) ? (size_t)(BIG_ROWS + kRing) * lds_stride(n_nodes) * sizeof(double) : 0;
+}
 
 hipError_t launch_cycle(const CycleDesc& cd, int prec, int threads, int grid, hipStream_t s)
 {
@@ -431,6 +468,7 @@ hipError_t launch_cycle(const CycleDesc& cd, int prec, int threads, int grid, hi
     c.ticket = cd.ticket;
     c.abort_flag = cd.abort_flag;
     c.plasma_ws = cd.plasma_ws;
+    c.big_rows = cd.big_rows;
     c.ring = cd.ring;
     c.slot_elems = cd.slot_elems;
     c.n_steps = cd.n_steps;

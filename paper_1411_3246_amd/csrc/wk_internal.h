@@ -115,12 +115,15 @@ struct CycleDesc {
     unsigned int* ticket;            // zeroed
     unsigned long long* abort_flag;  // counter slot, zeroed
     double* plasma_ws;               // grid * 4 * np doubles
+    double* big_rows;                // large grids: grid * cycle_big_rows_bytes
     void* ring;                      // 2 field slots
     int64_t slot_elems;
     int n_steps;
     double dt;
 };
 size_t cycle_lds_bytes(int n_nodes);
+// bytes of global node and beam rows per workgroup (0 unless the grid is large)
+size_t cycle_big_rows_bytes(int n_nodes);
 hipError_t launch_cycle(const CycleDesc& c, int prec, int threads, int grid, hipStream_t s);
 
 // Reverse-mode derivative of the witness gain (wk_adjoint.hip).

@@ -222,6 +222,7 @@ struct Acc {
 // thread's stores.
 template <typename R, int GEOM, bool WARM, int K, bool RESIDENT, bool BIG = false>
 struct Marcher {
+    static constexpr bool kBig = BIG;
     const MarchDesc d;
     double* sm;
     int st, N, N1, T, tid, lane, wid, blk;

@@ -340,3 +340,33 @@ def test_large_grid_mixed(O, W):
     f = _np(sim.fields)
     assert _l2(f[1], ref["fields"][1]) <= 1e-3
     assert _l2(f[0], ref["fields"][0]) <= 1e-3
+
+
+@pytest.mark.parametrize("n_r", [1000, 1200])
+def test_pipelined_cycle_large_grid(O, W, n_r):
+    """Large grids in the pipelined cycle (node rows and beam-current rows in
+    global memory; at 1000 cells only the cycle needs that, at 1200 the
+    sequential march too): same beam and fields as the sequential cycle and
+    the oracle, FP64."""
+    import torch
+    p = inputs.facet_two_bunch(n_r=n_r, n_xi=64, ppc=2, u_th=0.02, n_d=1.0, n_beam=4000, n_steps=3,
+                               prec="fp64", name=f"cycle-large-{n_r}")
+    print("case", p.name, flush=True)
+    seq = W.Simulation(p)
+    seq.load_beam()
+    for _ in range(p.n_steps):
+        seq.step()
+    pipe = W.Simulation(p)
+    pipe.load_beam()
+    pipe.run_cycle(p.n_steps)
+    torch.cuda.synchronize()
+    c = pipe.counters_dict()
+    assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0 and c["nonfinite"] == 0
+    a, b = _beam_np(pipe), _beam_np(seq)
+    for k in a:
+        scale = max(1.0, np.max(np.abs(b[k])))
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-10 * scale, k
+    assert _rel(_np(pipe.fields), _np(seq.fields)) <= 1e-10
+    ref = O.cycle(p, inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
+    assert _rel(_np(pipe.fields), ref["fields"]) <= 1e-9
+    assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-9)
