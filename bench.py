@@ -76,6 +76,9 @@ def parse():
                     help="skip the batched 256-instance parameter scan")
     ap.add_argument("--scan-instances", type=int, default=256)
     ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
+    ap.add_argument("--workload", choices=["headline", "convergence"], default="headline",
+                    help="convergence: the 2048-cell cylindrical (2048 x 16384) and slab (2048 x 8192) "
+                         "runs, 64 particles per cell, 4e6 beam particles, against the 512-cell runs")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the gradient (adjoint / forward time) measurement")
     ap.add_argument("--grad-reps", type=int, default=3)
@@ -218,6 +221,62 @@ def grad_bench(args):
     }
 
 
+def convergence_bench(args):
+    """Convergence-scale runs, each against the same two-bunch workload at
+    512 radial cells and a quarter of the slices (the headline grid).
+
+    For the cylindrical (2048 x 16384) and slab (2048 x 8192, x <= 8) grids
+    with 64 particles per cell and 4e6 beam particles: the first plasma
+    response is compared with the 512-cell one on the coarse nodes (every
+    4th node and slice): ||dE_z|| / ||E_z|| and the on-axis E_z spike behind
+    the drive at both resolutions; then `--steps` pipelined cycles are timed
+    (HIP events)."""
+    import numpy as np
+    import torch
+    from paper_1411_3246_amd import inputs, wake
+    out = {}
+    for geom in ("cyl", "slab"):
+        fine = inputs.convergence_cyl() if geom == "cyl" else inputs.convergence_slab()
+        coarse = fine.replace(n_r=fine.n_r // 4, n_xi=fine.n_xi // 4, ppc=16, n_beam=1_000_000,
+                              n_drive=int(round(1_000_000 / 1.3)), name=f"{fine.name}-coarse")
+        ez = {}
+        peak = {}
+        for tag, p in (("coarse", coarse), ("fine", fine)):
+            sim = wake.Simulation(p)
+            sim.load_beam()
+            sim.run_cycle(1)
+            torch.cuda.synchronize()
+            ez[tag] = sim.fields[1].double().cpu().numpy()
+            peak[tag] = sim.ez_peak(3.0)
+            print(f"# {geom} {tag} first response done", file=sys.stderr, flush=True)
+            del sim
+            torch.cuda.empty_cache()
+        ef = ez["fine"][::4, ::4]
+        ec = ez["coarse"]
+        rel = float(np.linalg.norm(ef - ec) / np.linalg.norm(ec))
+        sim = wake.Simulation(fine.replace(n_steps=args.steps))
+        sim.load_beam()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(torch.cuda.current_stream())
+        sim.run_cycle(args.steps)
+        ev[1].record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        upd = fine.updates_per_response() * args.steps
+        out[geom] = {
+            "workload": fine.name, "n_r": fine.n_r, "n_xi": fine.n_xi, "ppc": fine.ppc, "r_max": fine.r_max,
+            "n_beam": fine.n_beam, "steps": args.steps, "cycle_ms": ms, "updates": upd,
+            "updates_per_s": upd / (ms * 1e-3),
+            "ez_rel_l2_vs_512": rel, "ez_spike_fine": peak["fine"], "ez_spike_512": peak["coarse"],
+            "witness_gain": sim.witness_gain(), "counters": sim.counters_dict(),
+        }
+        print(f"# {geom} cycle {ms:.0f} ms", file=sys.stderr, flush=True)
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -228,6 +287,19 @@ def main():
     from paper_1411_3246_amd import inputs, wake
 
     torch.cuda.set_device(0)
+    if args.workload == "convergence":
+        conv = convergence_bench(args)
+        upd = sum(v["updates"] for v in conv.values())
+        ms = sum(v["cycle_ms"] for v in conv.values())
+        print(json.dumps({
+            "metric": "plasma particle-slice updates/s at 1 GPU", "value": upd / (ms * 1e-3),
+            "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+            "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+            "config": {"workload": "convergence-2048-cells (cylindrical 2048x16384 + slab 2048x8192)",
+                       "ppc": 64, "n_beam": 4_000_000, "beam_steps_timed": args.steps},
+            "convergence": conv}), flush=True)
+        return
     p = inputs.blowout_response().replace(n_steps=args.steps)
     sim = wake.Simulation(p, threads=args.threads)
     stream = torch.cuda.current_stream()
