@@ -238,7 +238,7 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
  * -> plasma response -> beam advance by dt (Section II A: the plasma responds
  * to the frozen beam, then the beam is advanced in t).  The responses of
  * successive steps run concurrently on separate workgroups: response n
- * marches slice k once response n-1 has stored the slices up to k + 3, and
+ * marches slice k once response n-1 has stored the slices up to k + 2, and
  * advances the beam particles of each xi bin just before it deposits them.
  * The result equals n_steps sequential calls of wk_beam_current,
  * wk_plasma_response (from the same loaded plasma) and wk_beam_push(1 step)

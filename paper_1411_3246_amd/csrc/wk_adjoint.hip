@@ -19,6 +19,8 @@
 // solve for B_theta, transposed scans for E_z and psi) and deposits (hat
 // gathers of the node adjoints).  The beam-current adjoint and the loaders'
 // chain rules then reduce everything to the five parameters.
+#include <algorithm>
+
 #include "wk_adjoint_dev.h"
 #include "wk_marcher.h"
 
@@ -894,7 +896,7 @@ hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double
         hipLaunchKernelGGL(kern, dim3(1), dim3(threads), bytes, s, d, tape, ckpt, every);
         return hipGetLastError();
     };
-    const size_t extra = 2 * (size_t)threads * kRecK * sizeof(double);
+    const size_t extra = 2 * (size_t)threads * std::min<int64_t>(kRecK, (d.np + threads - 1) / threads) * sizeof(double);
     const bool res = d.np <= (int64_t)threads * kRecK && lds + extra <= 159 * 1024;
     switch (threads) {
     case 256:

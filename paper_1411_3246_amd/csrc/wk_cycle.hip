@@ -17,6 +17,8 @@
 // each wait is bounded and sets an abort flag when exceeded so that every
 // workgroup drains.
 #include "wk_beam_dev.h"
+#include <algorithm>
+
 #include "wk_marcher.h"
 
 namespace wk {
@@ -31,8 +33,9 @@ __host__ __device__ inline bool cycle_needs_global_rows(int n_nodes)
 {
     return (size_t)(NUM_ROWS + kRing) * lds_stride(n_nodes) * sizeof(double) > 159 * 1024;
 }
-constexpr int kLag = 3;           // slices of response n-1 needed beyond a bin
-constexpr int kPublish = 4;       // slices between progress publications
+constexpr int kLag = 2;           // slices of response n-1 needed beyond a bin: a particle of
+                                  // bin b gathers slices b and b+1
+constexpr int kPublish = 1;       // slices between progress publications
 constexpr unsigned kSpinLimit = 1u << 26;
 
 struct CycleDescFull {
@@ -409,7 +412,8 @@ hipError_t launch_t(const CycleDescFull& c, int grid, hipStream_t s)
     if (cycle_needs_global_rows(c.base.n_r + 1)) return launch_big<R, GEOM, WARM>(c, grid, s);
     constexpr int K = cycle_tile<T>();
     const size_t lds = march_lds_bytes(c.base.n_r + 1, T) + (size_t)kRing * lds_stride(c.base.n_r + 1) * sizeof(double);
-    const size_t lds_res = lds + 2 * (size_t)T * K * sizeof(R);
+    const int64_t kr = std::min<int64_t>(K, (c.base.np + T - 1) / T);
+    const size_t lds_res = lds + 2 * (size_t)T * kr * sizeof(R);
     const bool res = c.base.np <= (int64_t)T * K && lds_res + 1024 <= 160 * 1024;
     if (res) {
         auto kern = k_cycle<R, GEOM, WARM, T, K, true>;

@@ -17,6 +17,8 @@
 // the whole workgroup.  Everything in the solves is double precision;
 // reciprocals there are refined to double accuracy.  In the mixed mode the
 // per-particle arithmetic uses the hardware float reciprocal and square root.
+#include <algorithm>
+
 #include "wk_marcher.h"
 
 namespace wk {
@@ -84,7 +86,9 @@ hipError_t launch_one_t(const MarchDesc& d, hipStream_t s)
     if (march_lds_bytes(d.n_r + 1, T) > kMaxLds) return launch_big<R, GEOM, WARM>(d, s);
     const size_t lds = march_lds_bytes(d.n_r + 1, T);
     constexpr int kK = tile_for(T);
-    const size_t lds_res = lds + 2 * (size_t)T * kK * sizeof(R);
+    // resident particles per thread (the kernel's own ceil(np / T))
+    const int64_t kr = std::min<int64_t>(kK, (d.np + T - 1) / T);
+    const size_t lds_res = lds + 2 * (size_t)T * kr * sizeof(R);
     // the whole instance stays on chip when its D0 and w fit in LDS
     const bool res = d.np <= (int64_t)T * kK && lds_res <= kMaxLds;
     if (res) {

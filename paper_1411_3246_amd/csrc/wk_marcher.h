@@ -226,6 +226,7 @@ struct Marcher {
     const MarchDesc d;
     double* sm;
     int st, N, N1, T, tid, lane, wid, blk;
+    int kr;   // resident particles per thread: ceil(np / T), at most K
     double h;
     R hR, ihR, rmaxR, dminR;
     unsigned long long clamps, walls;
@@ -239,12 +240,14 @@ struct Marcher {
     __device__ __forceinline__ Marcher(const MarchDesc& desc, double* smem, void* pconst = nullptr)
         : d(desc), sm(smem), clamps(0), walls(0)
     {
-        cd0 = (R*)pconst;
-        cw = cd0 ? cd0 + (int64_t)blockDim.x * K : nullptr;
         N = d.n_r;
         N1 = N + 1;
         st = (N1 + 1) & ~1;
         T = blockDim.x;
+        kr = RESIDENT ? (int)min((int64_t)K, (d.np + T - 1) / T) : K;
+        // D0 in slots [0, T kr), w in [T kr, 2 T kr) (the launch sizes LDS so)
+        cd0 = (R*)pconst;
+        cw = cd0 ? cd0 + (int64_t)T * kr : nullptr;
         tid = threadIdx.x;
         lane = tid & 63;
         wid = tid >> 6;
@@ -576,8 +579,8 @@ struct Marcher {
     __device__ __forceinline__ int block_of(int t) const
     {
         const int ppc = (int)(d.np / N);
-        if (ppc % K == 0) {
-            const int hpc = ppc / K;
+        if (kr > 0 && ppc % kr == 0) {
+            const int hpc = ppc / kr;
             const int W = T >> 6;
             if (hpc > 1 && W % hpc == 0) {
                 const int l = t & 63, w = t >> 6;
@@ -591,10 +594,10 @@ struct Marcher {
     __device__ __forceinline__ void for_parts(Fn fn)
     {
         if (RESIDENT) {
-            const int64_t i0 = (int64_t)blk * K;
+            const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                if (i0 + m < d.np) {
+                if (m < kr && i0 + m < d.np) {
                     Part<R> p;
                     p.x = X[m];
                     p.y = Y[m];
@@ -642,10 +645,10 @@ struct Marcher {
     __device__ __forceinline__ void for_idx(Fn fn)
     {
         if (RESIDENT) {
-            const int64_t i0 = (int64_t)blk * K;
+            const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                if (i0 + m < d.np) {
+                if (m < kr && i0 + m < d.np) {
                     Part<R> p;
                     p.x = X[m];
                     p.y = Y[m];
@@ -700,17 +703,19 @@ struct Marcher {
         }
         blk = block_of(tid);
         if (RESIDENT) {
-            const int64_t i0 = (int64_t)blk * K;
+            const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 Part<R> p = Part<R>{0.0, 0.0, 0.0, 0.0, (R)1, (R)0};
-                if (i0 + m < d.np) p = load(i0 + m);
+                if (m < kr && i0 + m < d.np) p = load(i0 + m);
                 X[m] = p.x;
                 Y[m] = p.y;
                 PX[m] = p.px;
                 PY[m] = p.py;
-                cd0[m * T + tid] = p.d0;
-                cw[m * T + tid] = p.w;
+                if (m < kr) {
+                    cd0[m * T + tid] = p.d0;
+                    cw[m * T + tid] = p.w;
+                }
             }
         }
         sync();
@@ -800,10 +805,10 @@ struct Marcher {
             }
         }
         if (RESIDENT) {
-            const int64_t i0 = (int64_t)blk * K;
+            const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m)
-                if (i0 + m < d.np) {
+                if (m < kr && i0 + m < d.np) {
                     Part<R> p;
                     p.x = X[m];
                     p.y = Y[m];
