@@ -76,7 +76,7 @@ def parse():
                     help="skip the batched 256-instance parameter scan")
     ap.add_argument("--scan-instances", type=int, default=256)
     ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
-    ap.add_argument("--workload", choices=["headline", "convergence"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "convergence", "te-scan"], default="headline",
                     help="convergence: the 2048-cell cylindrical (2048 x 16384) and slab (2048 x 8192) "
                          "runs, 64 particles per cell, 4e6 beam particles, against the 512-cell runs")
     ap.add_argument("--no-grad", action="store_true",
@@ -277,6 +277,36 @@ def convergence_bench(args):
     return out
 
 
+def te_scan_bench(args):
+    """The Table I driver (fixed beam) in a plasma at T_e = 0, 1, 2, 5, 10,
+    20, 30 eV on a 256 x 2800 grid over xi in [0, 14), and the slice-spacing
+    ladder dxi = 0.02 ... 0.00125 for a cold and a 5 eV plasma: every instance
+    in one batched launch; the on-axis E_z spike behind the drive and the
+    on-axis E_z at the witness centre per instance."""
+    import torch
+    from paper_1411_3246_amd import inputs, wake
+    probs = inputs.te_scan_instances(ladder=(700, 1400, 2800, 5600, 11200))
+    scan = wake.Scan(probs)
+    scan.threads = 1024
+    scan.run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(torch.cuda.current_stream())
+    scan.run()
+    ev[1].record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rows = []
+    xi_from = 3.5 * inputs.TABLE1["sigma_zd"] + 1.0
+    for q, pl, f in zip(probs, scan.plans, scan.fields):
+        pl.ez_peak(f, xi_from, out)
+        k = int((q.bunches[1].xi_c - q.xi_min) / q.dxi)
+        rows.append({"T_e_eV": round((q.u_th ** 2) * inputs.MC2_EV, 3), "dxi": q.dxi, "n_xi": q.n_xi,
+                     "ez_spike": float(out.item()), "ez_witness_axis": float(f[1, k, 0].item())})
+    return {"ms": ev[0].elapsed_time(ev[1]), "instances": len(probs), "updates": scan.updates,
+            "counters": wake.counters_dict(scan.counters), "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -299,6 +329,15 @@ def main():
             "config": {"workload": "convergence-2048-cells (cylindrical 2048x16384 + slab 2048x8192)",
                        "ppc": 64, "n_beam": 4_000_000, "beam_steps_timed": args.steps},
             "convergence": conv}), flush=True)
+        return
+    if args.workload == "te-scan":
+        ts = te_scan_bench(args)
+        print(json.dumps({
+            "metric": "plasma particle-slice updates/s at 1 GPU", "value": ts["updates"] / (ts["ms"] * 1e-3),
+            "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": ts["ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64",
+            "data": "synthetic", "config": {"workload": "table1-temperature-and-dxi-scan (256 cells, fixed beam)"},
+            "te_scan": ts}), flush=True)
         return
     p = inputs.blowout_response().replace(n_steps=args.steps)
     sim = wake.Simulation(p, threads=args.threads)

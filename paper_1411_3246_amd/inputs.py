@@ -147,6 +147,55 @@ def convergence_slab() -> Problem:
                            geom="slab", r_max=8.0, name="two-bunch-slab-2048x8192-ppc64")
 
 
+# Table I two-bunch driver in normalized units (n_p = 5e16 cm^-3, k_p^-1 = 23.7 um):
+# drive n = 3.56, sigma_z = 1.44; witness n = 2.85, sigma_z = 0.81, 5.48 behind;
+# common sigma_r = 0.42.
+TABLE1 = dict(n_d=3.56, n_w=2.85, sigma_r=0.42, sigma_zd=1.44, sigma_zw=0.81, sep=5.48)
+MC2_EV = 510998.95
+
+
+def u_th_of(t_e_ev: float) -> float:
+    """Thermal momentum spread per component (units of m_e c) of a plasma at
+    temperature T_e: u_th = sqrt(k T_e / m_e c^2)."""
+    return (t_e_ev / MC2_EV) ** 0.5 if t_e_ev > 0 else 0.0
+
+
+def facet_table1(t_e_ev: float = 0.0, n_r: int = 256, n_xi: int = 1400, ppc: int = 16,
+                 r_max: float = 6.0, xi_max: float = 14.0, prec: str = "mixed",
+                 seed: int = 0) -> Problem:
+    """The Table I FACET-like two-bunch driver as a fixed (analytic) beam on a
+    window [0, xi_max) with the drive centred 3.5 sigma_zd behind its head,
+    in a plasma at temperature t_e_ev (eV); ppc is made even when warm."""
+    t = TABLE1
+    xi_d = 3.5 * t["sigma_zd"]
+    u = u_th_of(t_e_ev)
+    if u > 0 and ppc % 2:
+        ppc += 1
+    return Problem(name=f"table1-T{t_e_ev:g}eV-{n_r}x{n_xi}", geom="cyl", n_r=n_r, r_max=r_max, n_xi=n_xi,
+                   xi_min=0.0, xi_max=xi_max, ppc=ppc, u_th=u, sigma_r=t["sigma_r"],
+                   bunches=[Bunch(t["n_d"], t["sigma_zd"], xi_d), Bunch(t["n_w"], t["sigma_zw"], xi_d + t["sep"])],
+                   n_beam=0, n_steps=0, prec=prec, seed=seed)
+
+
+def te_scan_instances(temps=(0.0, 1.0, 2.0, 5.0, 10.0, 20.0, 30.0), ladder=(700, 1400, 2800, 5600),
+                      ladder_temps=(0.0, 5.0), n_r: int = 256, n_xi: int = 2800, ppc: int = 16,
+                      prec: str = "mixed") -> List[Problem]:
+    """The temperature scan of the Table I driver at one resolution, and the
+    slice-spacing ladder for a cold and a 5 eV plasma (duplicates dropped)."""
+    out, seen = [], set()
+    for te in temps:
+        key = (te, n_xi)
+        seen.add(key)
+        out.append(facet_table1(te, n_r=n_r, n_xi=n_xi, ppc=ppc, prec=prec))
+    for te in ladder_temps:
+        for nx in ladder:
+            if (te, nx) in seen:
+                continue
+            seen.add((te, nx))
+            out.append(facet_table1(te, n_r=n_r, n_xi=nx, ppc=ppc, prec=prec))
+    return out
+
+
 def scan_instances(n: int = 256, seed: int = 0, prec: str = "mixed") -> List[Problem]:
     """Parameter scan of independent fixed-beam instances with uneven sizes:
     u_th ~ U[0, 0.05], separation ~ U[3, 6], n_r in {128, 256, 512, 1024},
