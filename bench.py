@@ -76,7 +76,8 @@ def parse():
                     help="skip the batched 256-instance parameter scan")
     ap.add_argument("--scan-instances", type=int, default=256)
     ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
-    ap.add_argument("--workload", choices=["headline", "convergence", "te-scan"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "convergence", "te-scan", "table1-beam"],
+                    default="headline",
                     help="convergence: the 2048-cell cylindrical (2048 x 16384) and slab (2048 x 8192) "
                          "runs, 64 particles per cell, 4e6 beam particles, against the 512-cell runs")
     ap.add_argument("--no-grad", action="store_true",
@@ -307,6 +308,44 @@ def te_scan_bench(args):
             "counters": wake.counters_dict(scan.counters), "rows": rows}
 
 
+def table1_beam_bench(args):
+    """The Table I beam (1e6 macroparticles, zero emittance) evolved over
+    1.14 m of plasma at 5e16 cm^-3 (1203 steps of 40 / omega_p) by the
+    pipelined cycle, in a cold and in a 5 eV plasma (256 x 2800 grid): the
+    witness mean gain and spread, the gain of the witness core (95th
+    percentile), the drive's mean energy change and the on-axis spike."""
+    import torch
+    from paper_1411_3246_amd import inputs, wake
+    out = {}
+    gev = 0.51099895e-3
+    for te in (0.0, 5.0):
+        p = inputs.facet_table1_beam(te)
+        sim = wake.Simulation(p)
+        sim.load_beam()
+        g0 = sim.beam["gamma_init"].clone()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(torch.cuda.current_stream())
+        sim.run_cycle(p.n_steps)
+        ev[1].record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        b = sim.beam
+        dg = torch.sqrt(1 + b["px"] ** 2 + b["py"] ** 2 + b["pz"] ** 2) - g0
+        wit = b["tag"] == 1
+        ms = ev[0].elapsed_time(ev[1])
+        out[f"{te:g}eV"] = {
+            "workload": p.name, "steps": p.n_steps, "ms": ms,
+            "updates_per_s": p.updates_per_response() * p.n_steps / (ms * 1e-3),
+            "witness_gain_gamma": sim.witness_gain(), "witness_gain_GeV": sim.witness_gain() * gev,
+            "witness_gain_std_gamma": float(dg[wit].std()),
+            "witness_core_gain_GeV": float(torch.quantile(dg[wit], 0.95)) * gev,
+            "drive_mean_dgamma": float(dg[~wit].mean()), "ez_spike_last": sim.ez_peak(6.04),
+            "counters": sim.counters_dict()}
+        print(f"# table1 beam {te:g} eV done", file=sys.stderr, flush=True)
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -329,6 +368,18 @@ def main():
             "config": {"workload": "convergence-2048-cells (cylindrical 2048x16384 + slab 2048x8192)",
                        "ppc": 64, "n_beam": 4_000_000, "beam_steps_timed": args.steps},
             "convergence": conv}), flush=True)
+        return
+    if args.workload == "table1-beam":
+        tb = table1_beam_bench(args)
+        upd = sum(v["updates_per_s"] * v["ms"] * 1e-3 for v in tb.values())
+        ms = sum(v["ms"] for v in tb.values())
+        print(json.dumps({
+            "metric": "plasma particle-slice updates/s at 1 GPU", "value": upd / (ms * 1e-3),
+            "unit": "updates/s", "n_gpus": 1, "steps": next(iter(tb.values()))["steps"], "warmup": 0,
+            "ms_per_step": ms / sum(v["steps"] for v in tb.values()), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+            "config": {"workload": "table1-beam-1.14m (256x2800, 16 ppc, 1e6 beam, cold and 5 eV)"},
+            "table1_beam": tb}), flush=True)
         return
     if args.workload == "te-scan":
         ts = te_scan_bench(args)

@@ -177,6 +177,21 @@ def facet_table1(t_e_ev: float = 0.0, n_r: int = 256, n_xi: int = 1400, ppc: int
                    n_beam=0, n_steps=0, prec=prec, seed=seed)
 
 
+def facet_table1_beam(t_e_ev: float = 0.0, n_r: int = 256, n_xi: int = 2800, ppc: int = 16,
+                      n_beam: int = 1_000_000, length_m: float = 1.14, dt: float = 40.0,
+                      prec: str = "mixed", seed: int = 0) -> Problem:
+    """The Table I driver as beam macroparticles (energy 4e4 m_e c^2, 0.1 %
+    spread, zero emittance) evolved over `length_m` metres of plasma at
+    n_p = 5e16 cm^-3 (k_p^-1 = 23.7 um) in steps of dt."""
+    p = facet_table1(t_e_ev, n_r=n_r, n_xi=n_xi, ppc=ppc, prec=prec, seed=seed)
+    t = TABLE1
+    q_ratio = (t["n_w"] * t["sigma_zw"]) / (t["n_d"] * t["sigma_zd"])
+    steps = int(round(length_m / 23.7e-6 / dt))
+    return p.replace(name=f"table1-beam-T{t_e_ev:g}eV-{n_r}x{n_xi}", n_beam=n_beam,
+                     n_drive=int(round(n_beam / (1.0 + q_ratio))), gamma0=4.0e4, rel_spread=1.0e-3,
+                     n_steps=steps, dt=dt)
+
+
 def te_scan_instances(temps=(0.0, 1.0, 2.0, 5.0, 10.0, 20.0, 30.0), ladder=(700, 1400, 2800, 5600),
                       ladder_temps=(0.0, 5.0), n_r: int = 256, n_xi: int = 2800, ppc: int = 16,
                       prec: str = "mixed") -> List[Problem]:
