@@ -66,3 +66,60 @@ def test_sizes_are_aligned_and_consistent():
     assert s.beam_current == p.n_xi * (p.n_r + 1) * 8
     for f in ("plasma_state", "plasma_const", "fields", "beam_current", "beam_state", "workspace"):
         assert getattr(s, f) % 256 == 0, f
+
+
+def test_gradient_workspace_validation():
+    """The gradient needs an FP64 plan with a two-bunch macroparticle beam;
+    otherwise the size query returns 0 and says why."""
+    import ctypes as C
+    from paper_1411_3246_amd import wake
+    L = wake.lib()
+    good = wake.Plan(inputs.facet_two_bunch(n_r=32, n_xi=64, ppc=4, n_beam=1000, prec="fp64"))
+    assert L.wk_gradient_workspace_size(good.handle, 20, 64) > 0
+    mixed = wake.Plan(inputs.facet_two_bunch(n_r=32, n_xi=64, ppc=4, n_beam=1000, prec="mixed"))
+    assert L.wk_gradient_workspace_size(mixed.handle, 20, 64) == 0
+    assert b"FP64" in L.wk_last_error()
+    fixed = wake.Plan(inputs.facet_two_bunch(n_r=32, n_xi=64, ppc=4, n_beam=0, prec="fp64"))
+    assert L.wk_gradient_workspace_size(fixed.handle, 20, 64) == 0
+    assert L.wk_gradient_workspace_size(good.handle, 20, 0) == 0
+    # larger checkpoint intervals need more segment scratch
+    assert L.wk_gradient_workspace_size(good.handle, 20, 128) > L.wk_gradient_workspace_size(good.handle, 20, 8)
+
+
+def test_batch_shape_validation():
+    """Launch-shape arguments are checked before any device work."""
+    import ctypes as C
+    from paper_1411_3246_amd import wake
+    L = wake.lib()
+    plans = [wake.Plan(inputs.weak_single_bunch(n_r=16, n_xi=32))]
+    h = (C.c_void_p * 1)(*[p.handle for p in plans])
+    ws = L.wk_batch_workspace_size(1, h)
+    fake = C.c_void_p(0x1000)
+    assert L.wk_batch_response_shape(1, h, fake, fake, ws, 300, 0, None) == -1
+    assert L.wk_batch_response_shape(1, h, fake, fake, ws, 256, 9, None) == -1
+    assert L.wk_batch_response_shape(1, h, fake, fake, ws - 1 if ws > 0 else 0, 256, 1, None) != 0
+
+
+def test_large_grid_plans_are_accepted():
+    """Up to 2048 radial cells: the plan workspace then carries the march's
+    global node rows."""
+    from paper_1411_3246_amd import wake
+    small = wake.Plan(inputs.weak_single_bunch(n_r=512))
+    big = wake.Plan(inputs.weak_single_bunch(n_r=2048))
+    assert big.sizes.workspace >= small.sizes.workspace + 11 * 2050 * 8
+
+
+def test_theta_roundtrip_and_table1_inputs():
+    import numpy as np
+    p = inputs.gradient_case()
+    th = inputs.theta_of(p)
+    q = inputs.with_theta(p, th * 1.1)
+    assert np.allclose(inputs.theta_of(q), th * 1.1)
+    assert q.bunches[1].n_peak == p.bunches[1].n_peak and q.bunches[1].sigma_z == p.bunches[1].sigma_z
+    assert inputs.u_th_of(0.0) == 0.0
+    assert abs(inputs.u_th_of(5.0) ** 2 * inputs.MC2_EV - 5.0) < 1e-9
+    probs = inputs.te_scan_instances()
+    keys = {(round(x.u_th, 12), x.n_xi) for x in probs}
+    assert len(keys) == len(probs)                      # no duplicates
+    b = inputs.facet_table1_beam(0.0)
+    assert b.n_steps == 1203 and b.n_drive + (b.n_beam - b.n_drive) == b.n_beam
