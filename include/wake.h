@@ -197,7 +197,8 @@ wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double*
  * solving psi, E_z and B_theta on every slice and storing
  * d_fields = real[4][n_xi][n_nodes] = psi, E_z, B_theta, W = E_r - B_theta.
  * d_jb: double[n_xi][n_nodes] beam current.  The plasma state is advanced in
- * place (load it again before the next response). */
+ * place (load it again before the next response).  Beyond about 1070
+ * cells the march keeps its field and solver rows in the plan workspace. */
 wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma,
                              const double* d_jb, void* d_fields, void* d_workspace,
                              uint64_t* d_counters, void* stream);
@@ -247,10 +248,11 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
  *   d_ring:   2 * sizes.fields bytes; the fields of response n are in slot
  *             n % 2, so the last response is in slot (n_steps - 1) % 2
  *   workspace: wk_cycle_workspace_size(plan, n_steps) bytes.
- * Requires n_r <= 880 (LDS).  Counter WK_CNT_PIPELINE_ABORT is set if a
- * workgroup waited too long for its predecessor (then the results are
- * invalid); WK_CNT_BEAM_BIN counts particles whose xi moved by more than a
- * slice during the run. */
+ * Any n_r up to 2048: beyond about 880 cells the node rows and the beam
+ * current rows live in the workspace instead of LDS.  Counter
+ * WK_CNT_PIPELINE_ABORT is set if a workgroup waited too long for its
+ * predecessor (then the results are invalid); WK_CNT_BEAM_BIN counts
+ * particles whose xi moved by more than a slice during the run. */
 size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps);
 wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_beam_bufs* beam,
                    int32_t n_steps, double dt, void* d_ring, void* d_workspace,

@@ -20,7 +20,7 @@ struct wk_plan {
     double h, dxi;
     wk::MarchShape shape;
     wk_sizes sizes;
-    size_t ws_fk_off, ws_beam_off;
+    size_t ws_beam_off;
     bool big;   // node rows beyond LDS: the march keeps its field rows in the workspace
 };
 
@@ -219,7 +219,6 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
     s.beam_state = a256(sizeof(double) * nb);
     s.beam_tag = a256(sizeof(int32_t) * nb);
     s.beam_draws = a256(sizeof(double) * 4 * nb);
-    pl->ws_fk_off = 0;
     // large grids: global node rows of the march first
     pl->big = wk::march_needs_global_rows(N1);
     pl->ws_beam_off = pl->big ? a256(wk::big_rows_bytes(N1)) : 0;
