@@ -370,3 +370,38 @@ def test_pipelined_cycle_large_grid(O, W, n_r):
     ref = O.cycle(p, inputs.plasma_draws(p), inputs.beam_draws(p), p.n_steps)
     assert _rel(_np(pipe.fields), ref["fields"]) <= 1e-9
     assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-9)
+
+
+def test_headline_cycle_full_size(O, W):
+    """The benchmark's workload and launch (512 x 4096, 16 ppc, 1e6 beam
+    particles, pipelined cycle, mixed precision): three steps against the
+    FP64 oracle's sequential cycle (last fields E_z within 1e-3, witness gain
+    within 1e-3); then, after 199 steps, the 200th response against the
+    oracle's response to the same (GPU-evolved) beam: E_z within 1e-3."""
+    import torch
+    p = inputs.blowout_response().replace(n_steps=3)
+    print("case", p.name, "3 steps", flush=True)
+    sim = W.Simulation(p)
+    sim.load_beam()
+    sim.run_cycle(3)
+    torch.cuda.synchronize()
+    ref = O.cycle(p.replace(prec="fp64"), inputs.plasma_draws(p), inputs.beam_draws(p), 3)
+    f = _np(sim.fields)
+    assert _l2(f[1], ref["fields"][1]) <= 1e-3
+    assert sim.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-3)
+    print("case", p.name, "199 + 1 steps", flush=True)
+    sim = W.Simulation(p.replace(n_steps=200))
+    sim.load_beam()
+    sim.run_cycle(199)
+    torch.cuda.synchronize()
+    beam = {k: _np(v) for k, v in sim.beam.items() if k != "tag"}
+    sim.run_cycle(1)
+    torch.cuda.synchronize()
+    c = sim.counters_dict()
+    assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0 and c["nonfinite"] == 0
+    q = p.replace(prec="fp64")
+    jb, _ = O.beam_current_macro(q, beam)
+    ref = O.response(q, inputs.plasma_draws(q), jb=jb)
+    f = _np(sim.fields)
+    assert _l2(f[1], ref["fields"][1]) <= 1e-3
+    assert _l2(f[0], ref["fields"][0]) <= 1e-3
