@@ -169,6 +169,12 @@ const char* wk_last_error(void);
  * kernel (safe under stream capture). */
 wk_status wk_counters_zero(uint64_t* d_counters, void* stream);
 
+/* Copy the counter array to h_out (WK_NCOUNTERS uint64, host memory),
+ * waiting for `stream`.  Returns WK_ERR_NUMERIC when non-finite field values
+ * were stored or a pipelined cycle gave up waiting (the results are then
+ * invalid), WK_OK otherwise; the other counters are informational. */
+wk_status wk_counters_read(const uint64_t* d_counters, uint64_t* h_out, void* stream);
+
 /* Plasma loader: ring macroparticles at cell-uniform radii; with u_th > 0,
  * mirrored pairs with momenta u_th * draws (d_draws: 3 standard normals per
  * pair, pair q = cell * ppc/2 + sub-radius) and flux weights a D0/gamma0;

@@ -256,6 +256,19 @@ wk_status wk_counters_zero(uint64_t* d_counters, void* stream)
                       "zero counters");
 }
 
+wk_status wk_counters_read(const uint64_t* d_counters, uint64_t* h_out, void* stream)
+{
+    if (!d_counters || !h_out) return fail(WK_ERR_INVALID_ARG, "NULL counters or output");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h_out, d_counters, sizeof(uint64_t) * WK_NCOUNTERS, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "read counters");
+    if (h_out[WK_CNT_NONFINITE] != 0)
+        return fail(WK_ERR_NUMERIC, "%llu non-finite field values", (unsigned long long)h_out[WK_CNT_NONFINITE]);
+    if (h_out[WK_CNT_PIPELINE_ABORT] != 0) return fail(WK_ERR_NUMERIC, "a pipelined cycle gave up waiting");
+    return WK_OK;
+}
+
 wk_status wk_init_plasma(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_draws, void* stream)
 {
     if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");

@@ -63,7 +63,7 @@ class WkBeamBufs(C.Structure):
 
 EXPORTS = [
     "wk_version", "wk_status_string", "wk_plan_create", "wk_plan_destroy", "wk_plan_sizes",
-    "wk_last_error", "wk_counters_zero", "wk_init_plasma", "wk_init_beam",
+    "wk_last_error", "wk_counters_zero", "wk_counters_read", "wk_init_plasma", "wk_init_beam",
     "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
@@ -100,6 +100,7 @@ def lib():
     L.wk_plan_threads.argtypes = [vp]
     L.wk_plan_threads.restype = i32
     L.wk_counters_zero.argtypes = [vp, vp]
+    L.wk_counters_read.argtypes = [vp, vp, vp]
     L.wk_init_plasma.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp]
     L.wk_init_beam.argtypes = [vp, C.POINTER(WkBeamBufs), vp, vp]
     L.wk_beam_current_analytic.argtypes = [vp, vp, vp]
@@ -306,6 +307,14 @@ def zero_counters(counters, stream=None):
 def counters_dict(counters) -> Dict[str, int]:
     v = counters.cpu().numpy()
     return {k: int(v[i]) for i, k in enumerate(COUNTER_NAMES)}
+
+
+def read_counters(counters, stream=None) -> Dict[str, int]:
+    """Counters through the library's own read-back; raises WakeError when
+    non-finite fields were stored or a pipelined cycle gave up waiting."""
+    out = (C.c_uint64 * NCOUNTERS)()
+    _check(lib().wk_counters_read(_ptr(counters), C.addressof(out), _stream(stream)), "wk_counters_read")
+    return {k: int(out[i]) for i, k in enumerate(COUNTER_NAMES)}
 
 
 # ---------------------------------------------------------------------------

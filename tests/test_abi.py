@@ -100,6 +100,16 @@ def test_batch_shape_validation():
     assert L.wk_batch_response_shape(1, h, fake, fake, ws - 1 if ws > 0 else 0, 256, 1, None) != 0
 
 
+def test_counter_read_rejects_null_pointers():
+    """The read-back checks its pointers before touching the device."""
+    import ctypes as C
+    from paper_1411_3246_amd import wake
+    L = wake.lib()
+    buf = (C.c_uint64 * wake.NCOUNTERS)()
+    assert L.wk_counters_read(None, C.addressof(buf), None) == -1
+    assert L.wk_counters_read(C.c_void_p(0x1000), None, None) == -1
+
+
 def test_large_grid_plans_are_accepted():
     """Up to 2048 radial cells: the plan workspace then carries the march's
     global node rows."""

@@ -77,6 +77,7 @@ def _check_fp64(O, W, p, tol=1e-10, threads=None):
         if np.max(np.abs(ref["state"][k])) > 0:
             assert _rel(st[k], ref["state"][k]) <= tol, k
     c = sim.counters_dict()
+    assert W.read_counters(sim.counters) == c        # the library's read-back agrees
     assert c["d_clamp"] == int(ref["counters"][0])
     assert c["wall"] == int(ref["counters"][1])
     assert c["nonfinite"] == 0
@@ -293,6 +294,7 @@ def test_pipelined_cycle_matches_sequential(O, W, prec):
     torch.cuda.synchronize()
     c = pipe.counters_dict()
     assert c["pipeline_abort"] == 0 and c["beam_bin"] == 0
+    assert W.read_counters(pipe.counters) == c
     a, b = _beam_np(pipe), _beam_np(seq)
     for k in a:
         scale = max(1.0, np.max(np.abs(b[k])))
