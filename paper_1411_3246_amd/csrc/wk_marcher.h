@@ -75,6 +75,14 @@ __device__ __forceinline__ double wave_scan_rounds(int n, int lane, const G& g, 
     return carry;
 }
 
+// LDS scratch of the block-wide scans: two buffers of per-wave totals (at
+// most 16 waves each).
+__device__ __forceinline__ double* scan_scratch()
+{
+    __shared__ double s[32];
+    return s;
+}
+
 // Store wait of the large-grid variant: its node rows partly live in global
 // memory, so a barrier must also wait for this thread's stores.
 template <bool GLOBAL_ROWS>
@@ -341,7 +349,11 @@ struct Marcher {
     {
         const double rmax = d.r_max;
         if (GEOM == WK_CYL) {
-            const double r = WARM ? sqrt(p.x * p.x + p.y * p.y) : fabs(p.x);
+            // r > r_max implies r^2 > r_max^2 (1 - 1e-12): the square root is
+            // taken only for particles that may have crossed
+            const double r2 = p.x * p.x + (WARM ? p.y * p.y : 0.0);
+            if (r2 <= rmax * rmax * (1.0 - 1e-12)) return;
+            const double r = WARM ? sqrt(r2) : fabs(p.x);
             if (r > rmax) {
                 double rn = 2.0 * rmax - r;
                 if (rn < 0.0) rn = 0.0;
@@ -447,32 +459,84 @@ struct Marcher {
         return (j == 0 || j == N) ? 2.0 * rcp64(h) : rcp64(h);
     }
 
-    // Wave 0: S -> psi.  Gauss fluxes F_{j+1/2} (prefix sum over the control
-    // volumes), u_j = -h F_{j+1/2} / r_{j+1/2}^a, psi_j = sum_{m >= j} u_m
-    // (psi_N = 0); then the node derivative psi'.
-    __device__ __forceinline__ void solve_psi(double* psi, double* dpsi)
+    // Items [j0, j1) of n owned by this thread in the blocked layout of the
+    // block-wide scans (q = ceil(n / T) consecutive items per thread).
+    __device__ __forceinline__ void owned(int n, int& j0, int& j1) const
+    {
+        const int q = (n + T - 1) / T;
+        j0 = min(tid * q, n);
+        j1 = min(j0 + q, n);
+    }
+
+    // Exclusive prefix in thread order of one value s per thread, and the
+    // workgroup total; wt holds the per-wave totals.  Contains a barrier, so
+    // every thread calls it.
+    __device__ __forceinline__ double block_excl(double s, double* wt, double& total) const
+    {
+        const double incl = wave_prefix(s);
+        if (lane == 63) wt[wid] = incl;
+        sync();
+        const int W = T >> 6;
+        double before = 0.0, tot = 0.0;
+        for (int w = 0; w < W; ++w) {
+            const double v = wt[w];
+            if (w < wid) before += v;
+            tot += v;
+        }
+        total = tot;
+        return before + incl - s;
+    }
+
+    // All threads: S -> psi.  Gauss fluxes F_{j+1/2} (prefix sums over the
+    // control volumes), u_j = -h F_{j+1/2} / r_{j+1/2}^a, psi_j = sum_{m >= j}
+    // u_m (psi_N = 0), as two block-wide scans.  psi' follows in
+    // finalize_moments.
+    __device__ __forceinline__ void solve_psi(double* psi)
     {
         const double* S = row(ROW_S);
         const double* nion = row(ROW_NION);
         const double c0 = GEOM == WK_CYL ? h * h / 8.0 : 0.5 * h;
-        wave_scan_rounds(
-            N, lane,
-            [&](int j) {
-                const double s = S[j] * inv_volume(j);
-                return j == 0 ? (s - nion[0]) * c0 : (s - nion[j]) * (GEOM == WK_CYL ? (double)j * h : 1.0) * h;
-            },
-            [&](int j, double, double incl) {
-                const double irph = GEOM == WK_CYL ? rcp64(((double)j + 0.5) * h) : 1.0;
-                psi[j] = -h * incl * irph;
-            });
-        wsync();
-        const double utot = wave_scan_rounds(
-            N, lane, [&](int j) { return psi[j]; }, [&](int j, double excl, double) { psi[j] = excl; });
-        wsync();
-        for (int j = lane; j < N1; j += 64) psi[j] = j < N ? utot - psi[j] : 0.0;
-        wsync();
+        const auto flux = [&](int j) {
+            const double s = S[j] * inv_volume(j);
+            return j == 0 ? (s - nion[0]) * c0 : (s - nion[j]) * (GEOM == WK_CYL ? (double)j * h : 1.0) * h;
+        };
+        const auto u_of = [&](int j, double F) {
+            const double irph = GEOM == WK_CYL ? rcp64(((double)j + 0.5) * h) : 1.0;
+            return -h * F * irph;
+        };
+        double* wt = scan_scratch();
+        int j0, j1;
+        owned(N, j0, j1);
+        double s1 = 0.0;
+        for (int j = j0; j < j1; ++j) s1 += flux(j);
+        double ftot, utot;
+        const double off1 = block_excl(s1, wt, ftot);
+        double F = off1, s2 = 0.0;
+        for (int j = j0; j < j1; ++j) {
+            F += flux(j);
+            s2 += u_of(j, F);
+        }
+        double U = block_excl(s2, wt + 16, utot);
+        F = off1;
+        for (int j = j0; j < j1; ++j) {
+            F += flux(j);
+            psi[j] = utot - U;
+            U += u_of(j, F);
+        }
+        if (tid == 0) psi[N] = 0.0;
+    }
+
+    // All threads: divide the deposits by the node volumes, add the beam
+    // current; and the node derivative psi' of this stage's psi.
+    __device__ __forceinline__ void finalize_moments(const double* jb_row)
+    {
+        const double* psi = row(ROW_PSI2);
+        double* dpsi = row(ROW_DPSI2);
         const double ih = rcp64(h);
-        for (int j = lane; j < N1; j += 64) {
+        for (int j = tid; j < N1; j += T) {
+            const double iv = inv_volume(j);
+            for (int r = ROW_JR; r <= ROW_M5; ++r) row(r)[j] = row(r)[j] * iv;
+            row(ROW_JZ)[j] += jb_row[j];
             double v;
             if (j == 0) v = 0.0;
             else if (j == N) v = (psi[N] - psi[N - 1]) * ih;
@@ -481,25 +545,23 @@ struct Marcher {
         }
     }
 
-    // All threads: divide the deposits by the node volumes, add the beam current.
-    __device__ __forceinline__ void finalize_moments(const double* jb_row)
-    {
-        for (int j = tid; j < N1; j += T) {
-            const double iv = inv_volume(j);
-            for (int r = ROW_JR; r <= ROW_M5; ++r) row(r)[j] = row(r)[j] * iv;
-            row(ROW_JZ)[j] += jb_row[j];
-        }
-    }
-
-    // Wave 0: E_z = -int_r^{r_max} J_r dr' (Eq. (7), trapezoid rule).
+    // All threads: E_z = -int_r^{r_max} J_r dr' (Eq. (7), trapezoid rule), a
+    // block-wide scan.
     __device__ __forceinline__ void solve_ez(double* ez)
     {
         const double* jr = row(ROW_JR);
-        const double tot = wave_scan_rounds(
-            N, lane, [&](int j) { return -(0.5 * h * (jr[j] + jr[j + 1])); },
-            [&](int j, double excl, double) { ez[j] = excl; });
-        wsync();
-        for (int j = lane; j < N1; j += 64) ez[j] = j < N ? tot - ez[j] : 0.0;
+        const auto w = [&](int j) { return -(0.5 * h * (jr[j] + jr[j + 1])); };
+        int j0, j1;
+        owned(N, j0, j1);
+        double s = 0.0;
+        for (int j = j0; j < j1; ++j) s += w(j);
+        double tot;
+        double run = block_excl(s, scan_scratch(), tot);
+        for (int j = j0; j < j1; ++j) {
+            ez[j] = tot - run;
+            run += w(j);
+        }
+        if (tid == 0) ez[N] = 0.0;
     }
 
     // All threads: B_theta from the Helmholtz form of Eq. (6) (rows 1..N-1) and
@@ -730,7 +792,7 @@ struct Marcher {
             const double* jb0 = hooks.jb_row(*this, k);
             // ---- stage 1 at (Y_k, xi_k): psi -> moments -> E_z, B ----
             sync();
-            if (wid == 0) solve_psi(psi2, dpsi2);
+            solve_psi(psi2);
             sync();
             {
                 Acc<R, 7> a;
@@ -741,7 +803,7 @@ struct Marcher {
             sync();
             finalize_moments(jb0);
             sync();
-            if (wid == 0) solve_ez(ez);
+            solve_ez(ez);
             sync();
             hooks.before_b(*this, k, 0);
             solve_b(dpsi2, ez, b1);
@@ -766,7 +828,7 @@ struct Marcher {
                 a.flush(row(ROW_S), st);
             }
             sync();
-            if (wid == 0) solve_psi(psi2, dpsi2);
+            solve_psi(psi2);
             sync();
             {
                 Acc<R, 7> a;
@@ -779,7 +841,7 @@ struct Marcher {
             sync();
             finalize_moments(hooks.jb_row(*this, k + 1));
             sync();
-            if (wid == 0) solve_ez(ez);
+            solve_ez(ez);
             sync();
             hooks.before_b(*this, k, 1);
             solve_b(dpsi2, ez, b2);
