@@ -92,7 +92,7 @@ template <int GEOM, bool WARM, int T, bool RES>
 __global__ __launch_bounds__(T) void k_march_record(MarchDesc d, double* tape, double* ckpt, int every)
 {
     extern __shared__ double smem[];
-    using M = dev::Marcher<double, GEOM, WARM, kRecK, RES>;
+    using M = dev::Marcher<double, GEOM, WARM, kRecK, RES, false, T>;
     M m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
     RecordHooks<M> hooks(tape, ckpt, every);
     m.run(hooks);
@@ -903,9 +903,11 @@ hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double
         return res ? go(k_march_record<GEOM, WARM, 256, true>, lds + extra) : go(k_march_record<GEOM, WARM, 256, false>, lds);
     case 512:
         return res ? go(k_march_record<GEOM, WARM, 512, true>, lds + extra) : go(k_march_record<GEOM, WARM, 512, false>, lds);
-    default:
+    case 1024:
         return res ? go(k_march_record<GEOM, WARM, 1024, true>, lds + extra)
                    : go(k_march_record<GEOM, WARM, 1024, false>, lds);
+    default:
+        return hipErrorInvalidValue;
     }
 }
 

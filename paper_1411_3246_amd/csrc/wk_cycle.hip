@@ -312,7 +312,7 @@ __global__ __launch_bounds__(T) void k_cycle(CycleDescFull c)
     extern __shared__ double smem[];
     __shared__ int s_n;
     __shared__ int wtot[T / 64];
-    using M = Marcher<R, GEOM, WARM, K, RES, BIG>;
+    using M = Marcher<R, GEOM, WARM, K, RES, BIG, T>;
     const int N1 = c.base.n_r + 1;
     const int st = lds_stride(N1);
     double* grow = BIG ? c.big_rows + (int64_t)blockIdx.x * (BIG_ROWS + kRing) * st : nullptr;

@@ -30,7 +30,7 @@ template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = fa
 __global__ __launch_bounds__(T) void k_march_one(MarchDesc d)
 {
     extern __shared__ double smem[];
-    Marcher<R, GEOM, WARM, K, RES, BIG> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+    Marcher<R, GEOM, WARM, K, RES, BIG, T> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
     m.run();
 }
 
@@ -51,10 +51,10 @@ __global__ __launch_bounds__(T) void k_march_batch(const MarchDesc* __restrict__
         if (i >= n) break;
         const MarchDesc d = descs[i];
         if (RES && d.np <= (int64_t)T * K) {
-            Marcher<R, GEOM, WARM, K, true> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+            Marcher<R, GEOM, WARM, K, true, false, T> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
             m.run();
         } else {
-            Marcher<R, GEOM, WARM, K, false> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
+            Marcher<R, GEOM, WARM, K, false, false, T> m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
             m.run();
         }
         __syncthreads();

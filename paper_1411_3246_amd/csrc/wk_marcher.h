@@ -92,15 +92,29 @@ __device__ __forceinline__ void block_sync()
     __syncthreads();
 }
 
+// Double value of lane `src` of the wavefront (two 32-bit permutes).
+__device__ __forceinline__ double lane_value(double v, int src)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Parallel cyclic reduction by the whole workgroup of the tridiagonal system
 // with rows (a, b, c, d) in buffer 0 (a[0] and c[n-1] ignored); buffer 1 is
-// scratch.  Solution in x.  One barrier per reduction step.
+// scratch.  Solution in x.  Reduction steps with strides 1, 2, 4, ... run in
+// memory with one barrier each until the rows of equal index modulo the
+// stride s form independent systems of at most 64 rows; each wavefront then
+// finishes its systems in registers (lane l holds row c + l s) with lane
+// permutes and no barrier.  Every step computes the same expressions as a
+// step in memory would.
 template <bool GLOBAL_ROWS = false>
 __device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, double* d0, double* a1, double* b1,
                           double* c1, double* d1, double* x, int n)
 {
     const int T = blockDim.x, tid = threadIdx.x;
-    for (int s = 1; s < n; s <<= 1) {
+    int s = 1;
+    for (; (n + s - 1) / s > 64; s <<= 1) {
         for (int i = tid; i < n; i += T) {
             double na = 0.0, nb = b0[i], nc = 0.0, nd = d0[i];
             if (i - s >= 0) {
@@ -127,7 +141,39 @@ __device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, do
         t = c0; c0 = c1; c1 = t;
         t = d0; d0 = d1; d1 = t;
     }
-    for (int i = tid; i < n; i += T) x[i] = d0[i] * rcp64(b0[i]);
+    const int lane = tid & 63;
+    for (int c = tid >> 6; c < s; c += T >> 6) {
+        const int m = (n - c + s - 1) / s;   // rows of system c
+        const int i = c + lane * s;
+        const bool on = lane < m;
+        double a = on ? a0[i] : 0.0, b = on ? b0[i] : 1.0, cc = on ? c0[i] : 0.0, d = on ? d0[i] : 0.0;
+        for (int t = 1; t < m; t <<= 1) {
+            const int lo = lane - t >= 0 ? lane - t : lane;
+            const int hi = lane + t < 64 ? lane + t : lane;
+            const double am = lane_value(a, lo), bm = lane_value(b, lo), cm = lane_value(cc, lo),
+                         dm = lane_value(d, lo);
+            const double ap = lane_value(a, hi), bp = lane_value(b, hi), cp = lane_value(cc, hi),
+                         dp = lane_value(d, hi);
+            double na = 0.0, nb = b, nc = 0.0, nd = d;
+            if (lane - t >= 0) {
+                const double k1 = a * rcp64(bm);
+                na = -am * k1;
+                nb -= cm * k1;
+                nd -= dm * k1;
+            }
+            if (lane + t < m) {
+                const double k2 = cc * rcp64(bp);
+                nc = -cp * k2;
+                nb -= ap * k2;
+                nd -= dp * k2;
+            }
+            a = na;
+            b = nb;
+            cc = nc;
+            d = nd;
+        }
+        if (on) x[i] = d * rcp64(b);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -224,11 +270,14 @@ struct Acc {
     }
 };
 
+// TB: the workgroup size when it is fixed at compile time (0: unknown); the
+// particle slots in LDS are then addressed with constant offsets.  Everything
+// else takes the size from blockDim.x.
 // BIG: the large-grid variant.  Only the deposit rows (S, J_r, J_z, M1..M5)
 // are in LDS; the field, ion and solver rows are in the descriptor's
 // per-workgroup global rows (d.grow), and every barrier first waits for the
 // thread's stores.
-template <typename R, int GEOM, bool WARM, int K, bool RESIDENT, bool BIG = false>
+template <typename R, int GEOM, bool WARM, int K, bool RESIDENT, bool BIG = false, int TB = 0>
 struct Marcher {
     static constexpr bool kBig = BIG;
     const MarchDesc d;
@@ -251,7 +300,7 @@ struct Marcher {
         N = d.n_r;
         N1 = N + 1;
         st = (N1 + 1) & ~1;
-        T = blockDim.x;
+        T = (int)blockDim.x;
         kr = RESIDENT ? (int)min((int64_t)K, (d.np + T - 1) / T) : K;
         // D0 in slots [0, T kr), w in [T kr, 2 T kr) (the launch sizes LDS so)
         cd0 = (R*)pconst;
@@ -265,6 +314,9 @@ struct Marcher {
         rmaxR = (R)d.r_max;
         dminR = (R)d.d_min;
     }
+
+    // workgroup size, a constant when TB is given
+    __device__ __forceinline__ int nt() const { return TB > 0 ? TB : T; }
 
     __device__ __forceinline__ double* row(int r) const
     {
@@ -665,8 +717,8 @@ struct Marcher {
                     p.y = Y[m];
                     p.px = PX[m];
                     p.py = PY[m];
-                    p.d0 = cd0[m * T + tid];
-                    p.w = cw[m * T + tid];
+                    p.d0 = cd0[m * nt() + tid];
+                    p.w = cw[m * nt() + tid];
                     fn(p);
                     if (STORE) {
                         X[m] = p.x;
@@ -716,8 +768,8 @@ struct Marcher {
                     p.y = Y[m];
                     p.px = PX[m];
                     p.py = PY[m];
-                    p.d0 = cd0[m * T + tid];
-                    p.w = cw[m * T + tid];
+                    p.d0 = cd0[m * nt() + tid];
+                    p.w = cw[m * nt() + tid];
                     fn(i0 + m, p);
                 }
             }
@@ -775,8 +827,8 @@ struct Marcher {
                 PX[m] = p.px;
                 PY[m] = p.py;
                 if (m < kr) {
-                    cd0[m * T + tid] = p.d0;
-                    cw[m * T + tid] = p.w;
+                    cd0[m * nt() + tid] = p.d0;
+                    cw[m * nt() + tid] = p.w;
                 }
             }
         }
