@@ -27,8 +27,6 @@
 namespace wk {
 namespace {
 
-using dev::wave_scan_rounds;
-using dev::wave_sync;
 
 constexpr int kTapeRows = 11;
 enum TapeRow { TP_PSI = 0, TP_DPSI, TP_EZ, TP_B, TP_JR, TP_JZ, TP_M1, TP_M2, TP_M3, TP_M4, TP_M5 };
@@ -185,6 +183,32 @@ struct Reverse {
     __device__ __forceinline__ double* row(int r) const { return sm + r * st; }
     __device__ __forceinline__ int64_t pidx(int m) const { return (int64_t)tid * a.kp + m; }
     __device__ __forceinline__ int64_t slot(int m) const { return (int64_t)m * kAdjT + tid; }
+
+    // Items [j0, j1) of n owned by this thread in the blocked layout of the
+    // block-wide scans (ceil(n / kAdjT) consecutive items per thread).
+    __device__ __forceinline__ void owned(int n, int& j0, int& j1) const
+    {
+        const int q = (n + kAdjT - 1) / kAdjT;
+        j0 = min(tid * q, n);
+        j1 = min(j0 + q, n);
+    }
+
+    // Exclusive prefix in thread order of one value per thread and the
+    // workgroup total; wt holds the per-wave totals.  Contains a barrier.
+    __device__ __forceinline__ double block_excl(double s, double* wt, double& total) const
+    {
+        const double incl = dev::wave_prefix(s);
+        if (lane == 63) wt[wid] = incl;
+        __syncthreads();
+        double before = 0.0, tot = 0.0;
+        for (int w = 0; w < kAdjT / 64; ++w) {
+            const double v = wt[w];
+            if (w < wid) before += v;
+            tot += v;
+        }
+        total = tot;
+        return before + incl - s;
+    }
 
     __device__ __forceinline__ adj::St get(const double* arr, int64_t s) const
     {
@@ -376,12 +400,22 @@ struct Reverse {
         }
         __syncthreads();
         // E_z = -int_r^{r_max} J_r (trapezoid): J_r adjoint from prefix sums
-        if (wid == 0) {
+        // (a block-wide scan)
+        {
             double* P = row(A_LAM);
-            wave_scan_rounds(
-                N, lane, [&](int j) { return row(A_EZ)[j]; }, [&](int j, double, double incl) { P[j] = incl; });
-            wave_sync();
-            for (int m = lane; m < N1; m += 64) {
+            const double* ezb = row(A_EZ);
+            int j0, j1;
+            owned(N, j0, j1);
+            double s = 0.0;
+            for (int j = j0; j < j1; ++j) s += ezb[j];
+            double tot;
+            double run = block_excl(s, dev::scan_scratch(), tot);
+            for (int j = j0; j < j1; ++j) {
+                run += ezb[j];
+                P[j] = run;
+            }
+            __syncthreads();
+            for (int m = tid; m < N1; m += kAdjT) {
                 const double pm = m <= N - 1 ? P[m] : 0.0;
                 const double pm1 = m >= 1 ? P[m - 1] : 0.0;
                 row(A_G0)[m] = -(0.5 * h) * (pm + pm1) * inv_volume(m);
@@ -390,8 +424,8 @@ struct Reverse {
         __syncthreads();
     }
 
-    // psi' adjoint -> psi adjoint; psi adjoint -> S adjoint (transposed scans);
-    // then clears the seed rows.  Wave 0 for the scans.
+    // psi' adjoint -> psi adjoint; psi adjoint -> S adjoint (transposed scans,
+    // block-wide).
     __device__ __forceinline__ void psi_reverse()
     {
         for (int t = tid; t < N1; t += kAdjT) {
@@ -406,29 +440,37 @@ struct Reverse {
         __syncthreads();
         for (int t = tid; t < N1; t += kAdjT) row(A_PSI)[t] += row(A_LAM)[t];
         __syncthreads();
-        if (wid == 0) {
-            double* F = row(A_LAM);
+        {
+            // F_j = -h / r_{j+1/2} * sum_{m <= j} psibar_m; Sbar_m from the
+            // suffix sums of F
             const double* pb = row(A_PSI);
-            wave_scan_rounds(
-                N, lane, [&](int j) { return pb[j]; },
-                [&](int j, double, double incl) {
-                    const double irph = GEOM == WK_CYL ? 1.0 / (((double)j + 0.5) * h) : 1.0;
-                    F[j] = -h * irph * incl;
-                });
-            wave_sync();
             double* S = row(A_S);
-            const double tot = wave_scan_rounds(
-                N, lane, [&](int j) { return F[j]; }, [&](int j, double excl, double) { S[j] = excl; });
-            wave_sync();
-            const double c0 = GEOM == WK_CYL ? h * h / 8.0 : 0.5 * h;
-            for (int m = lane; m < N1; m += 64) {
-                if (m < N) {
-                    const double coef = m == 0 ? c0 : (GEOM == WK_CYL ? (double)m * h : 1.0) * h;
-                    S[m] = (tot - S[m]) * coef * inv_volume(m);
-                } else {
-                    S[m] = 0.0;
-                }
+            double* wt = dev::scan_scratch();
+            const auto f_of = [&](int j, double incl) {
+                const double irph = GEOM == WK_CYL ? 1.0 / (((double)j + 0.5) * h) : 1.0;
+                return -h * irph * incl;
+            };
+            int j0, j1;
+            owned(N, j0, j1);
+            double s1 = 0.0;
+            for (int j = j0; j < j1; ++j) s1 += pb[j];
+            double t1, tot;
+            const double off1 = block_excl(s1, wt, t1);
+            double run = off1, s2 = 0.0;
+            for (int j = j0; j < j1; ++j) {
+                run += pb[j];
+                s2 += f_of(j, run);
             }
+            double e = block_excl(s2, wt + 16, tot);
+            const double c0 = GEOM == WK_CYL ? h * h / 8.0 : 0.5 * h;
+            run = off1;
+            for (int j = j0; j < j1; ++j) {
+                run += pb[j];
+                const double coef = j == 0 ? c0 : (GEOM == WK_CYL ? (double)j * h : 1.0) * h;
+                S[j] = (tot - e) * coef * inv_volume(j);
+                e += f_of(j, run);
+            }
+            if (tid == 0) S[N] = 0.0;
         }
         __syncthreads();
     }
