@@ -118,6 +118,15 @@ def test_fp64_warm_moderate(O, W):
     _check_fp64(O, W, p, tol=1e-9)
 
 
+@pytest.mark.parametrize("threads", [256, 512])
+def test_fp64_warm_one_particle_per_thread(O, W, threads):
+    """Warm two-bunch driver with one resident particle per thread at 256
+    threads (32 cells x 8 per cell): the particle-slot addressing with the
+    workgroup size as a compile-time constant."""
+    p = inputs.facet_two_bunch(n_r=32, n_xi=200, ppc=8, sep=3.5, u_th=0.02, n_beam=0, prec="fp64")
+    _check_fp64(O, W, p, tol=1e-9, threads=threads)
+
+
 def test_fp64_slab(O, W):
     p = inputs.weak_single_bunch(geom="slab", r_max=8.0, n_r=128, n_xi=256, n_b0=0.3)
     _check_fp64(O, W, p)
