@@ -148,7 +148,9 @@ enum wk_counter_index {
     WK_CNT_BEAM_OUT_DEPOSIT = 3,  /* beam particles outside the window (deposit) */
     WK_CNT_BEAM_OUT_PUSH = 4,  /* beam particle-steps outside the window (push) */
     WK_CNT_BEAM_BIN = 5,       /* beam particles that left their xi bin */
-    WK_CNT_PIPELINE_ABORT = 6, /* nonzero: a pipelined cycle gave up waiting (results invalid) */
+    WK_CNT_PIPELINE_ABORT = 6, /* nonzero: a wait between workgroups gave up (results invalid) */
+    WK_CNT_BEAM_ORDER = 7,     /* nonzero: a pipelined cycle lost beam particles from its xi bins
+                                  (results invalid) */
     WK_NCOUNTERS = 8
 };
 
@@ -171,8 +173,9 @@ wk_status wk_counters_zero(uint64_t* d_counters, void* stream);
 
 /* Copy the counter array to h_out (WK_NCOUNTERS uint64, host memory),
  * waiting for `stream`.  Returns WK_ERR_NUMERIC when non-finite field values
- * were stored or a pipelined cycle gave up waiting (the results are then
- * invalid), WK_OK otherwise; the other counters are informational. */
+ * were stored, a wait between workgroups gave up or a pipelined cycle lost
+ * beam particles from its bins (the results are then invalid), WK_OK
+ * otherwise; the other counters are informational. */
 wk_status wk_counters_read(const uint64_t* d_counters, uint64_t* h_out, void* stream);
 
 /* Plasma loader: ring macroparticles at cell-uniform radii; with u_th > 0,
@@ -209,11 +212,25 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma,
                              const double* d_jb, void* d_fields, void* d_workspace,
                              uint64_t* d_counters, void* stream);
 
-/* Launch shape: workgroup size of the march kernel (256, 512 or 1024).  The
- * plan picks one from the problem size; an autotuner may override it before
- * the plan is first used. */
+/* Launch shape: smallest workgroup size of the march kernel (256, 512 or
+ * 1024; the launch may use a larger one to keep the particles in
+ * registers).  The plan picks one from the problem size; an autotuner may
+ * override it before the plan is first used. */
 wk_status wk_plan_set_threads(wk_plan* plan, int32_t threads);
 int32_t wk_plan_threads(const wk_plan* plan);
+
+/* Workgroups that march one response together (1..16, at most n_r; 0 = chosen
+ * per call).  The response's plasma cells are split into `group` contiguous
+ * bands, one per workgroup; the deposits of the bands (S, the currents and
+ * the moments, Section II A) are summed between the workgroups in a fixed
+ * order through device memory four times per slice, and every workgroup
+ * solves the field equations on the identical sums.  Results do not depend
+ * on the group beyond the summation order of the deposits.  All workgroups
+ * of a group must run at once; the library sizes its launches so that they
+ * do, and a wait that exceeds 20 s sets WK_CNT_PIPELINE_ABORT instead of
+ * hanging.  wk_plan_group returns the group a single response uses. */
+wk_status wk_plan_set_group(wk_plan* plan, int32_t group);
+int32_t wk_plan_group(const wk_plan* plan);
 
 /* Batched responses (a parameter scan of independent instances, any mix of
  * sizes, all with the same geometry, precision and temperature class):
@@ -260,6 +277,10 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
  * predecessor (then the results are invalid); WK_CNT_BEAM_BIN counts
  * particles whose xi moved by more than a slice during the run. */
 size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps);
+/* Workgroups per response that wk_cycle uses for n_steps steps on the
+ * current device: the plan's group when set, else the largest group for
+ * which all responses are resident at once. */
+int32_t wk_cycle_group(const wk_plan* plan, int32_t n_steps);
 wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_beam_bufs* beam,
                    int32_t n_steps, double dt, void* d_ring, void* d_workspace,
                    size_t workspace_bytes, uint64_t* d_counters, void* stream);

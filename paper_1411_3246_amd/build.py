@@ -13,7 +13,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwake.so")
-SOURCES = ["wk_march.hip", "wk_cycle.hip", "wk_beam.hip", "wk_adjoint.hip", "wk_api.hip"]
+# the march and cycle kernels are instantiated per precision and geometry in
+# separate translation units so that they compile in parallel
+SOURCES = ["wk_march.hip", "wk_beam.hip", "wk_adjoint.hip", "wk_api.hip"] + [
+    f"wk_{kind}_{prec}_{geom}.hip" for kind in ("march", "cycle") for prec in ("f64", "f32")
+    for geom in ("cyl", "slab")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Werror",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,7 +40,8 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
     if verbose:

@@ -63,7 +63,7 @@ struct RecordHooks : M::NoRecord {
     {
         const int N1 = m.N1;
         double* t = tape + ((int64_t)k * 2 + stage) * kTapeRows * N1;
-        for (int j = m.tid; j < N1; j += m.T) {
+        for (int j = m.tid; j < N1; j += M::kT) {
             t[TP_PSI * N1 + j] = m.row(ROW_PSI2)[j];
             t[TP_DPSI * N1 + j] = m.row(ROW_DPSI2)[j];
             t[TP_EZ * N1 + j] = m.row(ROW_EZ)[j];
@@ -80,7 +80,7 @@ struct RecordHooks : M::NoRecord {
     {
         const int N1 = m.N1;
         double* t = tape + ((int64_t)k * 2 + stage) * kTapeRows * N1;
-        for (int j = m.tid; j < N1; j += m.T) t[TP_B * N1 + j] = bt[j];
+        for (int j = m.tid; j < N1; j += M::kT) t[TP_B * N1 + j] = bt[j];
     }
 };
 
@@ -90,7 +90,7 @@ template <int GEOM, bool WARM, int T, bool RES>
 __global__ __launch_bounds__(T) void k_march_record(MarchDesc d, double* tape, double* ckpt, int every)
 {
     extern __shared__ double smem[];
-    using M = dev::Marcher<double, GEOM, WARM, kRecK, RES, false, T>;
+    using M = dev::Marcher<double, GEOM, WARM, T, kRecK, RES, false>;
     M m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
     RecordHooks<M> hooks(tape, ckpt, every);
     m.run(hooks);

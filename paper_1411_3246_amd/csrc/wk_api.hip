@@ -18,7 +18,8 @@ struct wk_plan {
     int32_t N1;       // nodes
     int64_t np;       // plasma macroparticles per slice
     double h, dxi;
-    wk::MarchShape shape;
+    int32_t threads;  // preferred workgroup size (256, 512 or 1024)
+    int32_t group;    // workgroups per response (0: chosen per call)
     wk_sizes sizes;
     size_t ws_beam_off;
     bool big;   // node rows beyond LDS: the march keeps its field rows in the workspace
@@ -85,6 +86,27 @@ int default_threads(int64_t np)
     return 1024;
 }
 
+// Workgroups per response of a single march: the plan's choice, else about
+// one per 1024 particles, at most kMaxGroup and the number of cells.
+int single_group(const wk_plan* pl)
+{
+    const int G = pl->group > 0 ? pl->group
+                                : (int)std::min<int64_t>(wk::kMaxGroup, std::max<int64_t>(1, pl->np / 1024));
+    return std::max(1, std::min(G, pl->N));
+}
+
+// Particles of the largest workgroup share when G workgroups march a response.
+int64_t member_np(const wk_plan* pl, int G) { return (int64_t)((pl->N + G - 1) / G) * pl->p.ppc; }
+
+// March region at the start of a plan workspace: the large-grid node rows of
+// up to kMaxGroup workgroups, the group's partial rows and its counter.
+size_t march_grow_bytes(const wk_plan* pl) { return pl->big ? wk::kMaxGroup * a256(wk::big_rows_bytes(pl->N1)) : 0; }
+size_t march_xbuf_bytes(int N1, int G)
+{
+    return a256((size_t)G * wk::kXRows * wk::lds_stride(N1) * sizeof(double));
+}
+size_t march_region_bytes(const wk_plan* pl) { return march_grow_bytes(pl) + march_xbuf_bytes(pl->N1, wk::kMaxGroup) + 256; }
+
 bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 
 wk_status check_plasma(const wk_plan* pl, const wk_plasma_bufs* b)
@@ -137,6 +159,10 @@ wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double
     d.counters = (unsigned long long*)counters;
     d.cost = pl->np * (int64_t)pl->p.n_xi;
     d.grow = nullptr;
+    d.ppc = pl->p.ppc;
+    d.group = 1;
+    d.xbuf = nullptr;
+    d.gctr = nullptr;
     return d;
 }
 
@@ -203,8 +229,8 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
     pl->np = (int64_t)p->n_r * p->ppc;
     pl->h = p->r_max / p->n_r;
     pl->dxi = (p->xi_max - p->xi_min) / p->n_xi;
-    pl->shape.threads = default_threads(pl->np);
-    pl->shape.tile = 4;
+    pl->threads = default_threads(pl->np);
+    pl->group = 0;
     const size_t rs = real_size(*p);
     wk_sizes& s = pl->sizes;
     s.n_plasma = pl->np;
@@ -219,9 +245,10 @@ wk_status wk_plan_create(const wk_problem* p, wk_plan** out)
     s.beam_state = a256(sizeof(double) * nb);
     s.beam_tag = a256(sizeof(int32_t) * nb);
     s.beam_draws = a256(sizeof(double) * 4 * nb);
-    // large grids: global node rows of the march first
+    // the march region first (large-grid node rows, group exchange), then
+    // the beam binning
     pl->big = wk::march_needs_global_rows(N1);
-    pl->ws_beam_off = pl->big ? a256(wk::big_rows_bytes(N1)) : 0;
+    pl->ws_beam_off = march_region_bytes(pl);
     s.workspace = pl->ws_beam_off + a256(wk::beam_ws_bytes(p->n_xi, p->n_beam));
     s.counters = a256(sizeof(uint64_t) * WK_NCOUNTERS);
     *out = pl;
@@ -243,11 +270,22 @@ wk_status wk_plan_set_threads(wk_plan* plan, int32_t threads)
     if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");
     if (threads != 256 && threads != 512 && threads != 1024)
         return fail(WK_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
-    plan->shape.threads = threads;
+    plan->threads = threads;
     return WK_OK;
 }
 
-int32_t wk_plan_threads(const wk_plan* plan) { return plan ? plan->shape.threads : 0; }
+int32_t wk_plan_threads(const wk_plan* plan) { return plan ? plan->threads : 0; }
+
+wk_status wk_plan_set_group(wk_plan* plan, int32_t group)
+{
+    if (!plan) return fail(WK_ERR_INVALID_ARG, "NULL plan");
+    if (group < 0 || group > wk::kMaxGroup) return fail(WK_ERR_INVALID_ARG, "group must be 0..%d", wk::kMaxGroup);
+    if (group > plan->N) return fail(WK_ERR_INVALID_ARG, "group %d exceeds the %d cells", group, plan->N);
+    plan->group = group;
+    return WK_OK;
+}
+
+int32_t wk_plan_group(const wk_plan* plan) { return plan ? single_group(plan) : 0; }
 
 wk_status wk_counters_zero(uint64_t* d_counters, void* stream)
 {
@@ -265,7 +303,8 @@ wk_status wk_counters_read(const uint64_t* d_counters, uint64_t* h_out, void* st
     if (e != hipSuccess) return hip_status(e, "read counters");
     if (h_out[WK_CNT_NONFINITE] != 0)
         return fail(WK_ERR_NUMERIC, "%llu non-finite field values", (unsigned long long)h_out[WK_CNT_NONFINITE]);
-    if (h_out[WK_CNT_PIPELINE_ABORT] != 0) return fail(WK_ERR_NUMERIC, "a pipelined cycle gave up waiting");
+    if (h_out[WK_CNT_PIPELINE_ABORT] != 0) return fail(WK_ERR_NUMERIC, "a wait between workgroups gave up");
+    if (h_out[WK_CNT_BEAM_ORDER] != 0) return fail(WK_ERR_NUMERIC, "a pipelined cycle lost beam particles from its bins");
     return WK_OK;
 }
 
@@ -314,19 +353,92 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
     wk_status st = check_plasma(plan, plasma);
     if (st != WK_OK) return st;
-    wk::MarchDesc d = make_desc(plan, plasma, d_jb, d_fields, d_counters);
-    if (plan->big) d.grow = (double*)d_workspace;
-    return hip_status(wk::launch_march(d, plan->p.prec, plan->shape, (hipStream_t)stream), "plasma response");
+    const int G = single_group(plan);
+    const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec);
+    char* ws = (char*)d_workspace;
+    wk::MarchLaunch L{};
+    L.one = make_desc(plan, plasma, d_jb, d_fields, d_counters);
+    L.one.group = G;
+    L.one.xbuf = (double*)(ws + march_grow_bytes(plan));
+    L.one.gctr = (unsigned*)(ws + march_grow_bytes(plan) + march_xbuf_bytes(plan->N1, wk::kMaxGroup));
+    L.grow = plan->big ? (double*)ws : nullptr;
+    L.grow_stride = wk::lds_stride(plan->N1);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = wk::launch_zero_u32(L.one.gctr, 1, s);
+    if (e == hipSuccess)
+        e = wk::launch_march(L, plan->p.prec, plan->p.geom, L.one.warm, shape, G, plan->N1, s);
+    return hip_status(e, "plasma response");
 }
 
-size_t wk_batch_desc_bytes(int32_t n) { return n > 0 ? a256(sizeof(wk::MarchDesc) * (size_t)n) : 0; }
+size_t wk_batch_desc_bytes(int32_t n)
+{
+    if (n <= 0) return 0;
+    return a256(sizeof(wk::MarchDesc) * (size_t)n) + a256(sizeof(int) * 2 * wk::kMaxGroup * (size_t)n);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Work plan of a batch: instances longest first (by particle-slice updates),
+// each marched by G_i workgroups: enough to hold its particles in registers
+// (8192 per workgroup) and to bring its cost near the per-compute-unit
+// average of the batch, at most kMaxGroup and its number of cells.
+struct BatchSchedule {
+    std::vector<int> order;     // instance indices, longest first
+    std::vector<int> group;     // G of each instance (original index)
+    std::vector<size_t> xoff;   // exchange rows of each instance in the workspace (0: none)
+    int tickets = 0;
+    int64_t max_member = 0;     // particles of the largest workgroup share
+    int max_nodes = 0;
+    size_t ws = 0;
+};
+
+BatchSchedule batch_schedule(int n, const wk_plan* const* plans)
+{
+    BatchSchedule B;
+    B.group.resize(n);
+    B.xoff.assign(n, 0);
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) total += (double)plans[i]->np * plans[i]->p.n_xi;
+    const double per_cu = total / std::max(1, device_cus());
+    for (int i = 0; i < n; ++i) {
+        const wk_plan* pl = plans[i];
+        const double cost = (double)pl->np * pl->p.n_xi;
+        int G = pl->group > 0 ? pl->group
+                              : (int)std::max<double>(std::ceil((double)pl->np / 8192.0), std::ceil(cost / per_cu));
+        G = std::max(1, std::min({G, wk::kMaxGroup, pl->N}));
+        B.group[i] = G;
+        B.tickets += G;
+        B.max_member = std::max(B.max_member, member_np(pl, G));
+        B.max_nodes = std::max(B.max_nodes, pl->N1);
+    }
+    B.order.resize(n);
+    for (int i = 0; i < n; ++i) B.order[i] = i;
+    std::stable_sort(B.order.begin(), B.order.end(), [&](int a, int b) {
+        return (double)plans[a]->np * plans[a]->p.n_xi > (double)plans[b]->np * plans[b]->p.n_xi;
+    });
+    // workspace: ticket counter, one group counter per instance, exchange rows
+    size_t o = 256 + a256((size_t)n * wk::kCtrPad * sizeof(unsigned));
+    for (int i = 0; i < n; ++i)
+        if (B.group[i] > 1) {
+            B.xoff[i] = o;
+            o += march_xbuf_bytes(plans[i]->N1, B.group[i]);
+        }
+    B.ws = o;
+    return B;
+}
+
+}  // namespace
+
+extern "C" {
 
 size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans)
 {
     if (n <= 0 || !h_plans) return 0;
     for (int i = 0; i < n; ++i)
         if (!h_plans[i]) return 0;
-    return 256;  // work-queue counter
+    return batch_schedule(n, h_plans).ws;
 }
 
 wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_plasma_bufs* h_plasma,
@@ -338,26 +450,42 @@ wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_p
     const size_t need = wk_batch_workspace_size(n, h_plans);
     if (need == 0) return fail(WK_ERR_INVALID_ARG, "NULL plan in batch");
     if (workspace_bytes < need) return fail(WK_ERR_BUFFER, "batch workspace needs %zu bytes", need);
+    const BatchSchedule B = batch_schedule(n, h_plans);
     const wk_plan* p0 = h_plans[0];
+    bool any_warm = false;
+    for (int i = 0; i < n; ++i) any_warm |= h_plans[i]->p.u_th > 0.0;
     std::vector<wk::MarchDesc> descs((size_t)n);
-    for (int i = 0; i < n; ++i) {
+    char* ws = (char*)d_workspace;
+    for (int q = 0; q < n; ++q) {
+        const int i = B.order[q];
         const wk_plan* pl = h_plans[i];
         if (pl->p.prec != p0->p.prec || pl->p.geom != p0->p.geom)
             return fail(WK_ERR_UNSUPPORTED, "batch instances must share geometry and precision");
         wk_status st = check_plasma(pl, &h_plasma[i]);
         if (st != WK_OK) return st;
+        // a batch with a warm instance runs every instance on the warm path,
+        // which reads the transverse momenta of all of them
+        if (any_warm && (!h_plasma[i].d_py || (pl->p.geom == WK_CYL && !h_plasma[i].d_y)))
+            return fail(WK_ERR_BUFFER, "instance %d: a batch with warm instances needs y and py buffers for every "
+                                       "instance", i);
         if (pl->big) return fail(WK_ERR_UNSUPPORTED, "instance %d: n_r = %d is too large for a batch", i, pl->N);
         if (!h_jb[i] || !h_fields[i]) return fail(WK_ERR_INVALID_ARG, "NULL jb or fields for instance %d", i);
-        descs[i] = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], d_counters);
+        wk::MarchDesc d = make_desc(pl, &h_plasma[i], h_jb[i], h_fields[i], d_counters);
+        d.warm = any_warm ? 1 : 0;
+        d.group = B.group[i];
+        d.gctr = (unsigned*)(ws + 256) + (size_t)i * wk::kCtrPad;
+        d.xbuf = B.group[i] > 1 ? (double*)(ws + B.xoff[i]) : nullptr;
+        descs[q] = d;
     }
-    // cold instances run on the warm path when the batch mixes both
-    bool any_warm = false;
-    for (auto& d : descs) any_warm |= d.warm != 0;
-    for (auto& d : descs) d.warm = any_warm ? 1 : 0;
-    // longest first
-    std::stable_sort(descs.begin(), descs.end(),
-                     [](const wk::MarchDesc& a, const wk::MarchDesc& b) { return a.cost > b.cost; });
     std::memcpy(h_desc, descs.data(), sizeof(wk::MarchDesc) * (size_t)n);
+    int* tk = (int*)((char*)h_desc + a256(sizeof(wk::MarchDesc) * (size_t)n));
+    int t = 0;
+    for (int q = 0; q < n; ++q)
+        for (int r = 0; r < B.group[B.order[q]]; ++r) {
+            tk[2 * t] = q;
+            tk[2 * t + 1] = r;
+            ++t;
+        }
     return WK_OK;
 }
 
@@ -370,33 +498,25 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
         return fail(WK_ERR_INVALID_ARG, "threads must be 0, 256, 512 or 1024 (got %d)", threads);
     if (wg_per_cu < 0 || wg_per_cu > 8) return fail(WK_ERR_INVALID_ARG, "wg_per_cu must be 0..8 (got %d)", wg_per_cu);
-    int max_nodes = 0, plan_threads = 256;
-    int64_t min_np = INT64_MAX;
+    const BatchSchedule B = batch_schedule(n, h_plans);
     bool warm = false;
-    for (int i = 0; i < n; ++i) {
-        max_nodes = std::max(max_nodes, h_plans[i]->N1);
-        plan_threads = std::max(plan_threads, h_plans[i]->shape.threads);
-        min_np = std::min(min_np, h_plans[i]->np);
-        warm |= h_plans[i]->p.u_th > 0.0;
-    }
-    if (threads == 0) threads = plan_threads;
-    // the resident variant (decided per instance in the kernel) when some
-    // instance fits the registers; the launcher drops it if LDS cannot hold it
-    const bool resident = min_np <= (int64_t)threads * wk::march_tile(threads);
-    const size_t lds = wk::march_lds_bytes(max_nodes, threads);
-    // workgroups resident per CU: bounded by LDS (160 KB) and by 2048 threads
-    const int fit = (int)std::max<size_t>(1, std::min<size_t>((160 * 1024) / std::max<size_t>(lds, 1),
-                                                               (size_t)(2048 / threads)));
-    int per_cu = wg_per_cu > 0 ? std::min(wg_per_cu, fit) : std::min(fit, threads >= 1024 ? 1 : 2);
-    const int grid = std::min(n, device_cus() * per_cu);
+    for (int i = 0; i < n; ++i) warm |= h_plans[i]->p.u_th > 0.0;
+    const int prec = h_plans[0]->p.prec, geom = h_plans[0]->p.geom;
+    const int shape = wk::pick_shape(B.max_member, threads > 0 ? threads : 512, B.max_nodes, prec);
+    const int occ = wk::march_occupancy(prec, geom, warm ? 1 : 0, shape, B.max_nodes);
+    if (occ <= 0) return fail(WK_ERR_UNSUPPORTED, "batch: no resident workgroup fits (%d nodes)", B.max_nodes);
+    const int per_cu = wg_per_cu > 0 ? std::min<int>(wg_per_cu, occ) : occ;
+    const int grid = std::min(B.tickets, device_cus() * per_cu);
     hipStream_t s = (hipStream_t)stream;
-    unsigned int* next = (unsigned int*)d_workspace;
-    hipError_t e = wk::launch_zero_u32(next, 1, s);
+    // ticket counter and group counters start at zero (a kernel: capturable)
+    hipError_t e = wk::launch_zero_u32((unsigned*)d_workspace, (int64_t)(256 + (size_t)n * wk::kCtrPad * 4) / 4, s);
     if (e != hipSuccess) return hip_status(e, "batch queue");
-    wk::MarchShape shape{threads, 4};
-    return hip_status(wk::launch_march_batch((const wk::MarchDesc*)d_desc, n, max_nodes, h_plans[0]->p.geom,
-                                             warm ? 1 : 0, h_plans[0]->p.prec, shape, resident, grid, next, s),
-                      "batch response");
+    wk::MarchLaunch L{};
+    L.descs = (const wk::MarchDesc*)d_desc;
+    L.tickets = (const int*)((const char*)d_desc + a256(sizeof(wk::MarchDesc) * (size_t)n));
+    L.n_tickets = B.tickets;
+    L.next = (unsigned*)d_workspace;
+    return hip_status(wk::launch_march(L, prec, geom, warm ? 1 : 0, shape, grid, B.max_nodes, s), "batch response");
 }
 
 wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void* d_desc, void* d_workspace,
@@ -405,42 +525,77 @@ wk_status wk_batch_response(int32_t n, const wk_plan* const* h_plans, const void
     return wk_batch_response_shape(n, h_plans, d_desc, d_workspace, workspace_bytes, 0, 0, stream);
 }
 
+}  // extern "C"
+
 namespace {
 
-
+// Launch plan and workspace layout of a pipelined cycle.  G workgroups march
+// each response: the plan's choice, else the largest G (at most kMaxGroup and
+// the number of cells) for which all n_steps + 1 groups are resident at once.
 struct CycleLayout {
-    int grid;
-    size_t count, start, fill, order, progress, ticket, plasma, big, total;
+    int G = 1, shape = 0, grid = 1;
+    int64_t np_max = 0;   // particles of the largest workgroup share
+    size_t count, start, fill, order, progress, ticket, gctr, zero_end, plasma, big, xbuf, total;
 };
 
 CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
 {
     CycleLayout L;
+    const int prec = pl->p.prec, geom = pl->p.geom, warm = pl->p.u_th > 0.0 ? 1 : 0;
+    const int cus = device_cus();
+    const int gmax = std::min(wk::kMaxGroup, pl->N);
+    bool found = false;
+    for (int G = gmax; G >= 1 && !found; --G) {
+        if (pl->group > 0 && G != pl->group) continue;
+        const int shape = wk::pick_shape(member_np(pl, G), pl->threads, pl->N1, prec);
+        int occ = wk::cycle_occupancy(prec, geom, warm, shape, pl->N1);
+        if (occ <= 0) occ = 1;
+        const int cap = (cus * occ / G) * G;
+        if (cap < G) continue;
+        const int64_t want = (int64_t)(n_steps + 1) * G;
+        if (want <= cap || G == 1 || pl->group > 0) {
+            L.G = G;
+            L.shape = shape;
+            L.grid = (int)std::min<int64_t>(want, cap);
+            found = true;
+        }
+    }
+    L.np_max = member_np(pl, L.G);
+    const int G = L.G;
     const int nb = pl->p.n_xi + 1;
-    const size_t lds = wk::cycle_lds_bytes(pl->N1);
-    const size_t big = wk::cycle_big_rows_bytes(pl->N1);
-    const int threads = big ? 1024 : pl->shape.threads;
-    const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
-    L.grid = std::min(n_steps + 1, device_cus() * std::min(per_cu, 2048 / threads));
+    const bool stream = !wk::kShapes[L.shape].resident;
+    const bool big = wk::kShapes[L.shape].big;
     size_t o = 0;
-    L.count = o; o += a256(sizeof(unsigned) * nb);
-    L.start = o; o += a256(sizeof(unsigned) * 2 * (nb + 1));
-    L.fill = o; o += a256(sizeof(unsigned) * nb);
+    L.count = o; o += a256(sizeof(unsigned) * (size_t)G * nb);
+    L.start = o; o += a256(sizeof(unsigned) * 2 * (size_t)G * (nb + 1));
+    L.fill = o; o += a256(sizeof(unsigned) * (size_t)G * nb);
     L.order = o; o += a256(sizeof(unsigned) * 2 * (size_t)std::max<int64_t>(pl->p.n_beam, 1));
+    // zeroed before every launch: progress, ticket, group counters
     L.progress = o; o += a256(sizeof(unsigned) * (size_t)std::max(n_steps, 1));
     L.ticket = o; o += 256;
-    L.plasma = o; o += a256(sizeof(double) * 4 * (size_t)pl->np * (size_t)L.grid);
-    L.big = o; o += a256(big * (size_t)L.grid);
+    L.gctr = o; o += a256(sizeof(unsigned) * wk::kCtrPad * (size_t)(n_steps + 1));
+    L.zero_end = o;
+    L.plasma = o; o += stream ? a256(sizeof(double) * 4 * (size_t)L.np_max * (size_t)L.grid) : 0;
+    L.big = o; o += big ? a256(wk::big_rows_bytes(pl->N1) * (size_t)L.grid) : 0;
+    L.xbuf = o; o += G > 1 ? (size_t)n_steps * march_xbuf_bytes(pl->N1, G) : 0;
     L.total = o;
     return L;
 }
 
 }  // namespace
 
+extern "C" {
+
 size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps)
 {
     if (!plan || n_steps < 1) return 0;
     return cycle_layout(plan, n_steps).total;
+}
+
+int32_t wk_cycle_group(const wk_plan* plan, int32_t n_steps)
+{
+    if (!plan || n_steps < 1) return 0;
+    return cycle_layout(plan, n_steps).G;
 }
 
 wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_beam_bufs* beam, int32_t n_steps,
@@ -453,20 +608,19 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
     if (st != WK_OK) return st;
     st = check_beam(plan, beam);
     if (st != WK_OK) return st;
-    if (wk::cycle_lds_bytes(plan->N1) > 159 * 1024)
-        return fail(WK_ERR_UNSUPPORTED, "n_r = %d is too large for the pipelined cycle", plan->N);
     const CycleLayout L = cycle_layout(plan, n_steps);
     if (workspace_bytes < L.total) return fail(WK_ERR_BUFFER, "cycle workspace needs %zu bytes", L.total);
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_workspace;
     const wk::GridDesc g = grid_of(plan);
-    hipError_t e = wk::launch_zero_u32((unsigned*)(ws + L.progress), (int64_t)(L.plasma - L.progress) / 4, s);
+    hipError_t e = wk::launch_zero_u32((unsigned*)(ws + L.progress), (int64_t)(L.zero_end - L.progress) / 4, s);
     if (e != hipSuccess) return hip_status(e, "cycle init");
-    e = wk::launch_beam_bins(g, plan->p.n_beam, *beam, (unsigned*)(ws + L.count), (unsigned*)(ws + L.start),
-                             (unsigned*)(ws + L.fill), (unsigned*)(ws + L.order), s);
+    e = wk::launch_beam_bins_split(g, plan->p.n_beam, L.G, *beam, (unsigned*)(ws + L.count), (unsigned*)(ws + L.start),
+                                   (unsigned*)(ws + L.fill), (unsigned*)(ws + L.order), s);
     if (e != hipSuccess) return hip_status(e, "cycle binning");
     wk::CycleDesc c;
     c.base = make_desc(plan, plasma, nullptr, nullptr, d_counters);
+    c.base.group = L.G;
     c.beam = *beam;
     c.grid = g;
     c.bin_start = (unsigned*)(ws + L.start);
@@ -475,14 +629,15 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
     c.progress = (unsigned*)(ws + L.progress);
     c.ticket = (unsigned*)(ws + L.ticket);
     c.abort_flag = (unsigned long long*)(d_counters + WK_CNT_PIPELINE_ABORT);
-    c.plasma_ws = (double*)(ws + L.plasma);
-    c.big_rows = wk::cycle_big_rows_bytes(plan->N1) ? (double*)(ws + L.big) : nullptr;
+    c.plasma_ws = wk::kShapes[L.shape].resident ? nullptr : (double*)(ws + L.plasma);
+    c.big_rows = wk::kShapes[L.shape].big ? (double*)(ws + L.big) : nullptr;
+    c.xbuf = L.G > 1 ? (double*)(ws + L.xbuf) : nullptr;
+    c.gctr = (unsigned*)(ws + L.gctr);
     c.ring = d_ring;
     c.slot_elems = (int64_t)4 * plan->p.n_xi * plan->N1;
     c.n_steps = n_steps;
     c.dt = dt;
-    const int threads = c.big_rows ? 1024 : plan->shape.threads;
-    return hip_status(wk::launch_cycle(c, plan->p.prec, threads, L.grid, s), "cycle");
+    return hip_status(wk::launch_cycle(c, plan->p.prec, L.shape, L.grid, s), "cycle");
 }
 
 wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void* d_fields, int32_t n_steps,
@@ -562,7 +717,7 @@ GradLayout grad_layout(const wk_plan* pl, int32_t n_steps, int32_t every)
     L.hist = take(d * (size_t)(n_steps + 1) * 6 * nb);
     L.fbar = take(d * 4 * nxn);
     L.jbbar = take(d * nxn);
-    L.scratch = take(d * wk::adjoint_scratch_doubles(np, every, pl->shape.threads));
+    L.scratch = take(d * wk::adjoint_scratch_doubles(np, every, pl->threads));
     L.ybar = take(d * 4 * np);
     L.d0bar = take(d * np);
     L.wbar = take(d * np);
@@ -611,7 +766,7 @@ wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma,
         e = wk::launch_init_plasma(g, plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec, *plasma, d_plasma_draws, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (load)");
     const wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
-    e = wk::launch_march_record(md, plan->shape.threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt), every, s);
+    e = wk::launch_march_record(md, plan->threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt), every, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (march)");
     e = wk::launch_push_record(g, plan->p.n_beam, *beam, (const double*)d_fields, n_steps, dt,
                                (double*)(ws + L.hist), (unsigned long long*)d_counters, s);
@@ -644,7 +799,7 @@ wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma
     gd.n_drive = plan->p.n_drive;
     gd.n_steps = n_steps;
     gd.every = every;
-    gd.threads = plan->shape.threads;
+    gd.threads = plan->threads;
     gd.dt = dt;
     gd.n_d = plan->p.bunch[0].n_peak;
     gd.sigma_r = plan->p.sigma_r;

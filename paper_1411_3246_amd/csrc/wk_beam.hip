@@ -220,19 +220,43 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const unsigned int* count,
     if (tid == 0) start[n] = carry;
 }
 
-__global__ void k_bin_count(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* count)
+// Subset of particle i when n particles are split into G contiguous ranges
+// [n s / G, n (s + 1) / G).
+__device__ inline int subset_of(int64_t i, int64_t n, int G)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    atomicAdd(count + dev::beam_xi_bin(g, b.d_xi[i]), 1u);
+    int s = (int)((i * G) / n);
+    while (s + 1 < G && n * (s + 1) / G <= i) ++s;
+    while (s > 0 && n * s / G > i) --s;
+    return s;
 }
 
-__global__ void k_bin_scatter(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* fill, unsigned int* order)
+__global__ void k_bin_count_split(GridDesc g, int64_t n, int G, const double* xi, unsigned int* count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const unsigned int pos = atomicAdd(fill + dev::beam_xi_bin(g, b.d_xi[i]), 1u);
-    order[pos] = (unsigned int)i;
+    const int s = subset_of(i, n, G);
+    atomicAdd(count + (int64_t)s * (g.n_xi + 1) + dev::beam_xi_bin(g, xi[i]), 1u);
+}
+
+__global__ void k_bin_scatter_split(GridDesc g, int64_t n, int G, const double* xi, unsigned int* fill,
+                                    unsigned int* order)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = subset_of(i, n, G);
+    const unsigned int pos = atomicAdd(fill + (int64_t)s * (g.n_xi + 1) + dev::beam_xi_bin(g, xi[i]), 1u);
+    order[pos] = (unsigned int)(i - n * s / G);
+}
+
+// Per-subset bin starts relative to the subset's first particle:
+// out[s][b] for b = 0..n_xi+1 from the global starts of the (subset, bin) keys.
+__global__ void k_split_starts(int nb, int64_t n, int G, const unsigned int* start_all, unsigned int* out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)G * (nb + 1)) return;
+    const int s = (int)(q / (nb + 1)), b = (int)(q % (nb + 1));
+    const int64_t b0 = n * s / G;
+    out[q] = b < nb ? (unsigned int)(start_all[(int64_t)s * nb + b] - b0) : (unsigned int)(n * (s + 1) / G - b0);
 }
 
 __global__ void k_beam_scatter(GridDesc g, int64_t n, wk_beam_bufs b, unsigned int* fill,
@@ -484,17 +508,26 @@ hipError_t launch_beam_current(const GridDesc& g, int64_t n_beam, const wk_beam_
     return hipGetLastError();
 }
 
-hipError_t launch_beam_bins(const GridDesc& g, int64_t n_beam, const wk_beam_bufs& b, unsigned int* count,
-                            unsigned int* bin_start, unsigned int* fill, unsigned int* order, hipStream_t s)
+hipError_t launch_beam_bins_split(const GridDesc& g, int64_t n_beam, int group, const wk_beam_bufs& b,
+                                  unsigned int* count, unsigned int* bin_start, unsigned int* fill,
+                                  unsigned int* order, hipStream_t s)
 {
     const int nb = g.n_xi + 1;
-    hipError_t e = launch_zero_u32(count, nb, s);
+    const int64_t keys = (int64_t)group * nb;
+    // the global starts of the keys go to the second slot of bin_start
+    // (G (nb + 1) >= keys + 1 entries), which the cycle writes later
+    unsigned int* start_all = bin_start + (int64_t)group * (nb + 1);
+    hipError_t e = launch_zero_u32(count, keys, s);
     if (e != hipSuccess) return e;
     if (n_beam > 0)
-        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, b, count);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, count, nb, bin_start, fill);
+        hipLaunchKernelGGL(k_bin_count_split, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, group,
+                           (const double*)b.d_xi, count);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, count, (int)keys, start_all, fill);
     if (n_beam > 0)
-        hipLaunchKernelGGL(k_bin_scatter, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, b, fill, order);
+        hipLaunchKernelGGL(k_bin_scatter_split, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, group,
+                           (const double*)b.d_xi, fill, order);
+    hipLaunchKernelGGL(k_split_starts, dim3(nblocks((int64_t)group * (nb + 1), kBlock)), dim3(kBlock), 0, s, nb,
+                       n_beam, group, start_all, bin_start);
     return hipGetLastError();
 }
 

@@ -42,11 +42,20 @@ __device__ __forceinline__ int beam_xi_bin(const GridDesc& g, double xi)
     return k > g.n_xi - 1 ? g.n_xi - 1 : k;
 }
 
+// Field value for the push: a plain load, or (COH) a device-coherent load of
+// fields that another compute unit stored during the same launch.
+template <bool COH, typename R>
+__device__ __forceinline__ double field_at(const R* p)
+{
+    if (COH) return (double)__hip_atomic_load(const_cast<R*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (double)*p;
+}
+
 // Eqs. (8)-(11) for an electron (q = -1) in the frozen fields: E = (E_r x/r,
 // E_r y/r, E_z), B = B_theta e_theta with E_r = W + B_theta, bilinear in
 // (r, xi); Boris rotation; d xi/dt = (1 + p_perp^2) / (gamma (gamma + p_z)).
 // Returns the number of steps taken outside the window (zero fields).
-template <typename R>
+template <typename R, bool COH = false>
 __device__ __forceinline__ unsigned long long beam_push_particle(const GridDesc& g, const R* __restrict__ fields,
                                                         double& x, double& y, double& xi, double& px,
                                                         double& py, double& pz, int n_steps, double dt)
@@ -75,10 +84,12 @@ __device__ __forceinline__ unsigned long long beam_push_particle(const GridDesc&
             const double w00 = (1.0 - tr) * (1.0 - tk1), w01 = tr * (1.0 - tk1);
             const double w10 = (1.0 - tr) * tk1, w11 = tr * tk1;
             const int64_t o0 = (int64_t)k * N1 + j, o1 = (int64_t)k1 * N1 + j;
-            ez = w00 * (double)fez[o0] + w01 * (double)fez[o0 + 1] + w10 * (double)fez[o1] +
-                 w11 * (double)fez[o1 + 1];
-            bt = w00 * (double)fb[o0] + w01 * (double)fb[o0 + 1] + w10 * (double)fb[o1] + w11 * (double)fb[o1 + 1];
-            wv = w00 * (double)fw[o0] + w01 * (double)fw[o0 + 1] + w10 * (double)fw[o1] + w11 * (double)fw[o1 + 1];
+            ez = w00 * field_at<COH>(fez + o0) + w01 * field_at<COH>(fez + o0 + 1) +
+                 w10 * field_at<COH>(fez + o1) + w11 * field_at<COH>(fez + o1 + 1);
+            bt = w00 * field_at<COH>(fb + o0) + w01 * field_at<COH>(fb + o0 + 1) + w10 * field_at<COH>(fb + o1) +
+                 w11 * field_at<COH>(fb + o1 + 1);
+            wv = w00 * field_at<COH>(fw + o0) + w01 * field_at<COH>(fw + o0 + 1) + w10 * field_at<COH>(fw + o1) +
+                 w11 * field_at<COH>(fw + o1 + 1);
         } else {
             ++out;
         }

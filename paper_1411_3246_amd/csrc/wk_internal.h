@@ -17,7 +17,7 @@ struct MarchDesc {
     int32_t warm;        // 1: transverse momenta / p_y present
     int32_t n_r;         // cells; nodes 0..n_r
     int32_t n_xi;        // stored slices
-    int64_t np;          // macroparticles in a slice
+    int64_t np;          // macroparticles in a slice (n_r * ppc)
     double r_max, h, dxi, d_min;
     double* x;
     double* y;
@@ -30,8 +30,19 @@ struct MarchDesc {
     void* fields;        // real[4][n_xi][n_r+1]
     unsigned long long* counters;
     int64_t cost;        // np * n_xi (scheduling weight)
-    double* grow;        // large grids: global node rows (BIG_ROWS x stride doubles)
+    double* grow;        // large grids: global node rows, BIG_ROWS x stride doubles per workgroup
+    int32_t ppc;         // macroparticles per cell
+    int32_t group;       // workgroups that march this response together (1..kMaxGroup)
+    double* xbuf;        // group > 1: partial deposit rows, [group][kXRows][stride] doubles
+    unsigned int* gctr;  // group > 1: arrival counter of the group barrier (own 256-byte line)
 };
+
+// Largest number of workgroups marching one response.
+constexpr int kMaxGroup = 16;
+// Deposit rows exchanged between the workgroups of a group (S, J_r, J_z, M1..M5).
+constexpr int kXRows = 8;
+// Spacing of the group counters (unsigned ints): one 256-byte line each.
+constexpr int kCtrPad = 64;
 
 // LDS rows used by the march kernel (each of `stride` doubles): the deposit
 // rows, the field rows of both Heun stages, the ion density and the scratch
@@ -55,20 +66,53 @@ inline size_t march_lds_bytes(int n_nodes, int /*threads*/)
     return (size_t)NUM_ROWS * lds_stride(n_nodes) * sizeof(double);
 }
 
-// Launch shapes (chosen by the plan).
-struct MarchShape {
-    int threads;   // workgroup size
-    int tile;      // particles per thread per tile (compile-time variant)
+// Kernel shapes of the march and of the pipelined cycle: workgroup size,
+// particles per thread (resident: held in registers for the whole march;
+// streamed: tiles of T * kp particles), and the large-grid variant whose
+// field rows live in global memory.
+struct ShapeInfo {
+    int threads, kp;
+    bool resident, big;
 };
-
-hipError_t launch_march(const MarchDesc& d, int prec, MarchShape shape, hipStream_t stream);
-hipError_t launch_march_batch(const MarchDesc* d_descs, int n, int max_nodes, int geom, int warm,
-                              int prec, MarchShape shape, bool resident, int grid,
-                              unsigned int* d_next, hipStream_t stream);
-// particles per thread per tile of the march kernel at a workgroup size
-int march_tile(int threads);
-// true when the node rows of a grid exceed LDS (large-grid variant)
+enum ShapeId {
+    SH_256_4 = 0, SH_512_4, SH_512_16, SH_1024_8, SH_1024_STREAM, SH_BIG_1024_8, SH_BIG_STREAM, NUM_SHAPES
+};
+constexpr ShapeInfo kShapes[NUM_SHAPES] = {
+    {256, 4, true, false}, {512, 4, true, false}, {512, 16, true, false}, {1024, 8, true, false},
+    {1024, 8, false, false}, {1024, 8, true, true}, {1024, 8, false, true},
+};
+// LDS bytes of a shape for grids of up to n_nodes nodes (rows, plus the
+// resident D0 / w slots when they are not kept in registers).
+size_t shape_lds_bytes(int shape, int n_nodes, int prec);
+// true when the node rows of a grid exceed LDS (large-grid shapes)
 bool march_needs_global_rows(int n_nodes);
+// The shape for `np` particles per workgroup on a grid of n_nodes nodes: the
+// smallest resident shape of at least `threads` threads that holds them and
+// fits LDS, else a streamed one.
+int pick_shape(int64_t np, int threads, int n_nodes, int prec);
+
+// One launch of the march kernel: a single response (descs == nullptr; its
+// `group` workgroups are the grid) or a batch (workgroups take tickets; each
+// ticket is one workgroup of one instance's group).
+struct MarchLaunch {
+    const MarchDesc* descs;   // batch: device array of instances
+    MarchDesc one;            // single response
+    const int* tickets;       // batch: [n_tickets][2] = (instance, rank)
+    int n_tickets;
+    unsigned int* next;       // batch: ticket counter (zeroed)
+    double* grow;             // large grids: grid * BIG_ROWS * grow_stride doubles
+    int grow_stride;
+};
+hipError_t launch_march(const MarchLaunch& L, int prec, int geom, int warm, int shape, int grid, int max_nodes,
+                        hipStream_t s);
+// workgroups of a march shape resident per compute unit (0: does not fit)
+int march_occupancy(int prec, int geom, int warm, int shape, int max_nodes);
+// per-(precision, geometry) launchers (wk_march_*.hip)
+// (occ != nullptr: only report the resident workgroups per compute unit)
+hipError_t launch_march_f64_cyl(const MarchLaunch& L, int warm, int shape, int grid, size_t lds, hipStream_t s, int* occ);
+hipError_t launch_march_f64_slab(const MarchLaunch& L, int warm, int shape, int grid, size_t lds, hipStream_t s, int* occ);
+hipError_t launch_march_f32_cyl(const MarchLaunch& L, int warm, int shape, int grid, size_t lds, hipStream_t s, int* occ);
+hipError_t launch_march_f32_slab(const MarchLaunch& L, int warm, int shape, int grid, size_t lds, hipStream_t s, int* occ);
 
 // Beam / loader kernels (wk_beam.hip)
 struct GridDesc {
@@ -98,33 +142,37 @@ hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t s);
 // Workspace layout of the beam binning (bytes, 256-aligned pieces).
 size_t beam_ws_bytes(int n_xi, int64_t n_beam);
 
-// Bin the beam by xi cell (bin n_xi: outside the window): bin_start has
-// n_xi + 2 entries, order n_beam.  count/fill are scratch of n_xi + 1.
-hipError_t launch_beam_bins(const GridDesc& g, int64_t n_beam, const wk_beam_bufs& b, unsigned int* count,
-                            unsigned int* bin_start, unsigned int* fill, unsigned int* order, hipStream_t s);
-
-// Pipelined quasi-static cycle (wk_cycle.hip).
+// Pipelined quasi-static cycle (wk_cycle_impl.h).  The beam is split into
+// `group` contiguous subsets; workgroup g of every response handles subset g
+// and keeps its own xi bins of it.
 struct CycleDesc {
-    MarchDesc base;                  // plasma template (loaded), constants, counters
+    MarchDesc base;                  // plasma template (loaded), constants, counters, group
     wk_beam_bufs beam;
     GridDesc grid;
-    unsigned int* bin_start;         // [2][n_xi + 2], slot 0 filled by launch_beam_bins
-    unsigned int* order;             // [2][n_beam]
+    unsigned int* bin_start;         // [2][group][n_xi + 2] per-subset bin starts (slot 0 filled
+                                     // by launch_beam_bins_split); bin n_xi: outside the window
+    unsigned int* order;             // [2][n_beam] subset-relative indices sorted by bin
     int64_t n_beam;
-    unsigned int* progress;          // n_steps counters (zeroed)
+    unsigned int* progress;          // [n_steps] stored slices per response (zeroed)
     unsigned int* ticket;            // zeroed
     unsigned long long* abort_flag;  // counter slot, zeroed
-    double* plasma_ws;               // grid * 4 * np doubles
-    double* big_rows;                // large grids: grid * cycle_big_rows_bytes
+    double* plasma_ws;               // streamed particles: grid * 4 * (largest subset) doubles
+    double* big_rows;                // large grids: grid * BIG_ROWS node rows
+    double* xbuf;                    // group > 1: [n_steps + 1][group][kXRows][stride] doubles
+    unsigned int* gctr;              // group > 1: [n_steps + 1] counters, kCtrPad apart (zeroed)
     void* ring;                      // 2 field slots
     int64_t slot_elems;
     int n_steps;
     double dt;
 };
-size_t cycle_lds_bytes(int n_nodes);
-// bytes of global node and beam rows per workgroup (0 unless the grid is large)
-size_t cycle_big_rows_bytes(int n_nodes);
-hipError_t launch_cycle(const CycleDesc& c, int prec, int threads, int grid, hipStream_t s);
+hipError_t launch_cycle(const CycleDesc& c, int prec, int shape, int grid, hipStream_t s);
+int cycle_occupancy(int prec, int geom, int warm, int shape, int n_nodes);
+// Bin each of `group` contiguous beam subsets by xi cell: bin_start gets
+// [group][n_xi + 2] subset-relative starts, order the subset-relative indices.
+// count/fill: scratch of group * (n_xi + 1) entries each.
+hipError_t launch_beam_bins_split(const GridDesc& g, int64_t n_beam, int group, const wk_beam_bufs& b,
+                                  unsigned int* count, unsigned int* bin_start, unsigned int* fill,
+                                  unsigned int* order, hipStream_t s);
 
 // Reverse-mode derivative of the witness gain (wk_adjoint.hip).
 struct GradDesc {

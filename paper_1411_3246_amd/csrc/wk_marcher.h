@@ -1,5 +1,13 @@
 // Device-side march of one plasma response (shared by the single, batched and
-// pipelined launches).  Internal header of libwake.
+// pipelined launches and by the recording forward of the adjoint).  Internal
+// header of libwake.
+//
+// A response may be marched by a group of G workgroups: workgroup g owns the
+// plasma macroparticles of a contiguous band of cells, deposits them into its
+// own LDS rows, and the G partial rows are summed between the workgroups in a
+// fixed order through device memory (four exchanges per slice).  Every
+// workgroup then solves the radial field equations itself on the identical
+// sums, so all of them gather the same fields.
 #pragma once
 
 #include "wk_internal.h"
@@ -27,6 +35,74 @@ template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __bu
 template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
 
 // --------------------------------------------------------------------------
+// Device-coherent accesses.  Data that another compute unit reads during the
+// same launch (partial deposit rows, stored fields of the pipelined cycle,
+// beam particles and their bins) is written and read with agent-scope
+// atomic accesses, which bypass the caches that are not coherent across
+// compute units and accelerator dies.  A writer waits for its stores to be
+// acknowledged (wait_vm) before it signals, so a reader that has seen the
+// signal reads the new values.  No cache-wide writeback or invalidation is
+// needed.
+// --------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ V ld_dev(const V* p)
+{
+    return __hip_atomic_load(const_cast<V*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ void st_dev(V* p, V v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Bounded waits: a wait gives up after kWaitTicks of the constant-rate
+// device clock (wall_clock64, 100 MHz) and raises the abort counter, so a
+// launch whose workgroups cannot all run at once ends with an error instead
+// of hanging.
+constexpr unsigned long long kWaitTicks = 2000000000ull;   // 20 s at 100 MHz
+
+// Thread 0 only: spin until *p >= need or the abort flag is set.
+__device__ __forceinline__ void wait_at_least(const unsigned* p, unsigned need, unsigned long long* abort_flag)
+{
+    if (ld_dev(p) >= need) return;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ld_dev(p) >= need) return;
+        if (ld_dev(abort_flag)) return;
+        if (wall_clock64() - t0 > kWaitTicks) {
+            st_dev(abort_flag, 1ull);
+            return;
+        }
+    }
+}
+
+// The workgroups that march one response together.
+struct Group {
+    int G = 1;                           // workgroups in the group
+    int g = 0;                           // this workgroup's rank
+    double* xbuf = nullptr;              // [G][kXRows][stride] partial rows
+    unsigned* ctr = nullptr;             // arrival counter
+    unsigned long long* abort = nullptr;
+    unsigned epoch = 0;                  // barriers passed
+};
+
+// All threads: every thread's device-coherent stores are complete; arrive at
+// the group barrier and wait for the other workgroups of the group.
+__device__ __forceinline__ void group_barrier(Group& grp)
+{
+    wait_vm();
+    __syncthreads();
+    ++grp.epoch;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(grp.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_at_least(grp.ctr, grp.epoch * (unsigned)grp.G, grp.abort);
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------------------
 // Wave-level prefix sums with DPP row shifts and row broadcasts
 // --------------------------------------------------------------------------
 template <int CTRL, int ROWMASK>
@@ -49,32 +125,6 @@ __device__ __forceinline__ double wave_prefix(double v)
     return v;
 }
 
-__device__ __forceinline__ double lane63(double v)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); __builtin_amdgcn_wave_barrier(); }
-
-// Exclusive prefix sums of g(j), j = 0..n-1, by one wavefront in rounds of
-// 64 consecutive items (lane l holds item 64 r + l).  fn(j, excl, incl) is
-// called for every item; returns the total.
-template <class G, class Fn>
-__device__ __forceinline__ double wave_scan_rounds(int n, int lane, const G& g, const Fn& fn)
-{
-    double carry = 0.0;
-    for (int base = 0; base < n; base += 64) {
-        const int j = base + lane;
-        const double v = j < n ? g(j) : 0.0;
-        const double incl = wave_prefix(v);
-        if (j < n) fn(j, carry + incl - v, carry + incl);
-        carry += lane63(incl);
-    }
-    return carry;
-}
-
 // LDS scratch of the block-wide scans: two buffers of per-wave totals (at
 // most 16 waves each).
 __device__ __forceinline__ double* scan_scratch()
@@ -88,7 +138,7 @@ __device__ __forceinline__ double* scan_scratch()
 template <bool GLOBAL_ROWS>
 __device__ __forceinline__ void block_sync()
 {
-    if (GLOBAL_ROWS) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (GLOBAL_ROWS) wait_vm();
     __syncthreads();
 }
 
@@ -110,7 +160,7 @@ __device__ __forceinline__ double lane_value(double v, int src)
 // step in memory would.
 template <bool GLOBAL_ROWS = false>
 __device__ __forceinline__ void block_pcr(double* a0, double* b0, double* c0, double* d0, double* a1, double* b1,
-                          double* c1, double* d1, double* x, int n)
+                                          double* c1, double* d1, double* x, int n)
 {
     const int T = blockDim.x, tid = threadIdx.x;
     int s = 1;
@@ -232,28 +282,33 @@ struct Part {
     R d0, w;
 };
 
+// Stage derivative d(x, y, px, py)/dxi of one particle, in the precision of
+// the per-particle arithmetic.
+template <typename R>
 struct Deriv {
-    double fx, fy, fpx, fpy;
+    R fx, fy, fpx, fpy;
 };
 
 // Register accumulator of NR deposit rows for the current cell of a thread.
+// The per-particle terms are formed in the particle precision R and summed in
+// double.
 template <typename R, int NR>
 struct Acc {
     int j;
-    R lo[NR], hi[NR];
+    double lo[NR], hi[NR];
     __device__ __forceinline__ void reset(int jj)
     {
         j = jj;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            lo[r] = (R)0;
-            hi[r] = (R)0;
+            lo[r] = 0.0;
+            hi[r] = 0.0;
         }
     }
     __device__ __forceinline__ void add(int r, const Rad<R>& q, R v)
     {
-        lo[r] += v * ((R)1 - q.t);
-        hi[r] += v * q.t;
+        lo[r] += (double)(v * ((R)1 - q.t));
+        hi[r] += (double)(v * q.t);
     }
     // Add the sums to NR consecutive LDS rows starting at `first` (row r at
     // first + r * stride); row `skip` is left out.
@@ -263,45 +318,60 @@ struct Acc {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r != skip) {
-                atomicAdd(first + r * stride + j, (double)lo[r]);
-                atomicAdd(first + r * stride + j + 1, (double)hi[r]);
+                atomicAdd(first + r * stride + j, lo[r]);
+                atomicAdd(first + r * stride + j + 1, hi[r]);
             }
         }
     }
 };
 
-// TB: the workgroup size when it is fixed at compile time (0: unknown); the
-// particle slots in LDS are then addressed with constant offsets.  Everything
-// else takes the size from blockDim.x.
+// T: workgroup size.  K: particles per thread (resident) or per tile
+// (streamed).  RES: the particles stay in registers for the whole march.
 // BIG: the large-grid variant.  Only the deposit rows (S, J_r, J_z, M1..M5)
 // are in LDS; the field, ion and solver rows are in the descriptor's
 // per-workgroup global rows (d.grow), and every barrier first waits for the
 // thread's stores.
-template <typename R, int GEOM, bool WARM, int K, bool RESIDENT, bool BIG = false, int TB = 0>
+//
+// The descriptor a Marcher gets is its own workgroup's share of the response:
+// the particle pointers and count are those of its band of cells, the grid
+// and field pointers those of the whole response.
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = false>
 struct Marcher {
     static constexpr bool kBig = BIG;
-    const MarchDesc d;
+    static constexpr int kT = T;
+    // With few resident particles per thread, D0 and w live in registers
+    // (else in LDS slots) and the stage-1 derivative is kept in registers
+    // between the three passes that use it (else recomputed).
+    static constexpr bool kRegConst = RES && (K <= 4 || (K <= 8 && sizeof(R) == 4));
+    static constexpr bool kCacheF = kRegConst;
+    MarchDesc d;
     double* sm;
-    int st, N, N1, T, tid, lane, wid, blk;
+    int st, N, N1, tid, lane, wid, blk;
     int kr;   // resident particles per thread: ceil(np / T), at most K
     double h;
     R hR, ihR, rmaxR, dminR;
     unsigned long long clamps, walls;
-    // resident state: positions and momenta in registers, D0 and w in LDS
-    // (slot m * threads + tid)
-    double X[RESIDENT ? K : 1], Y[RESIDENT ? K : 1], PX[RESIDENT ? K : 1], PY[RESIDENT ? K : 1];
+    Group grp;
+    bool stores;        // this workgroup writes the fields
+    bool keep_state;    // write the final resident state back to d.x ... d.py
+    // resident state: positions and momenta in registers
+    double X[RES ? K : 1], Y[RES ? K : 1], PX[RES ? K : 1], PY[RES ? K : 1];
+    R D0r[kRegConst ? K : 1], Wr[kRegConst ? K : 1];
+    R FX[kCacheF ? K : 1], FY[kCacheF ? K : 1], FPX[kCacheF ? K : 1], FPY[kCacheF ? K : 1];
     R* cd0;
     R* cw;
 
-    // pconst: LDS for the resident D0 and w (2 * threads * K reals)
-    __device__ __forceinline__ Marcher(const MarchDesc& desc, double* smem, void* pconst = nullptr)
-        : d(desc), sm(smem), clamps(0), walls(0)
+    // pconst: LDS for the resident D0 and w when they are not in registers
+    // (2 * T * K reals)
+    __device__ __forceinline__ Marcher(const MarchDesc& desc, double* smem, void* pconst = nullptr,
+                                       const Group& group = Group(), bool store_fields = true,
+                                       bool keep = true)
+        : d(desc), sm(smem), clamps(0), walls(0), grp(group), stores(store_fields), keep_state(keep)
     {
         N = d.n_r;
         N1 = N + 1;
         st = (N1 + 1) & ~1;
-        T = (int)blockDim.x;
-        kr = RESIDENT ? (int)min((int64_t)K, (d.np + T - 1) / T) : K;
+        kr = RES ? (int)min((int64_t)K, (d.np + T - 1) / T) : K;
         // D0 in slots [0, T kr), w in [T kr, 2 T kr) (the launch sizes LDS so)
         cd0 = (R*)pconst;
         cw = cd0 ? cd0 + (int64_t)T * kr : nullptr;
@@ -315,19 +385,11 @@ struct Marcher {
         dminR = (R)d.d_min;
     }
 
-    // workgroup size, a constant when TB is given
-    __device__ __forceinline__ int nt() const { return TB > 0 ? TB : T; }
-
     __device__ __forceinline__ double* row(int r) const
     {
         return (BIG && r >= ROW_PSI1) ? d.grow + (int64_t)(r - ROW_PSI1) * st : sm + r * st;
     }
     __device__ __forceinline__ void sync() const { block_sync<BIG>(); }
-    __device__ __forceinline__ void wsync() const
-    {
-        if (BIG) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        ::wk::dev::wave_sync();
-    }
 
     __device__ __forceinline__ Part<R> load(int64_t i) const
     {
@@ -351,22 +413,22 @@ struct Marcher {
         }
     }
 
-    __device__ __forceinline__ static Part<R> advance(const Part<R>& p, const Deriv& g, double dt)
+    __device__ __forceinline__ static Part<R> advance(const Part<R>& p, const Deriv<R>& g, double dt)
     {
         Part<R> q = p;
-        q.x = p.x + dt * g.fx;
-        q.px = p.px + dt * g.fpx;
+        q.x = p.x + dt * (double)g.fx;
+        q.px = p.px + dt * (double)g.fpx;
         if (GEOM == WK_CYL && WARM) {
-            q.y = p.y + dt * g.fy;
-            q.py = p.py + dt * g.fpy;
+            q.y = p.y + dt * (double)g.fy;
+            q.py = p.py + dt * (double)g.fpy;
         }
         return q;
     }
 
     // Eqs. (4)-(5) in the transverse Cartesian frame, with the field rows of
     // one stage (psi, psi', B_theta).
-    __device__ __forceinline__ Deriv derivative(const Part<R>& p, const double* psi, const double* dpsi,
-                                const double* bt) const
+    __device__ __forceinline__ Deriv<R> derivative(const Part<R>& p, const double* psi, const double* dpsi,
+                                                   const double* bt) const
     {
         const Rad<R> q = radial<R, GEOM, WARM>(p.x, p.y, rmaxR, hR, ihR, N);
         R D = p.d0 + gather(psi, q);
@@ -377,22 +439,22 @@ struct Marcher {
         const R iD = frcp(D);
         const R gam = ((R)1 + p2 + D * D) * ((R)0.5 * iD);
         const R F = (gam * iD) * gather(dpsi, q) - gather(bt, q);
-        Deriv g;
-        g.fx = (double)(px * iD);
+        Deriv<R> g;
+        g.fx = px * iD;
         if (GEOM == WK_CYL) {
-            g.fy = WARM ? (double)(py * iD) : 0.0;
+            g.fy = WARM ? py * iD : (R)0;
             if (q.r > (R)0) {
                 const R fr = q.sw * F * frcp(q.r);
-                g.fpx = (double)(fr * (R)p.x);
-                g.fpy = WARM ? (double)(fr * (R)p.y) : 0.0;
+                g.fpx = fr * (R)p.x;
+                g.fpy = WARM ? fr * (R)p.y : (R)0;
             } else {
-                g.fpx = 0.0;
-                g.fpy = 0.0;
+                g.fpx = (R)0;
+                g.fpy = (R)0;
             }
         } else {
-            g.fy = 0.0;
-            g.fpx = (double)(q.sg * F);
-            g.fpy = 0.0;
+            g.fy = (R)0;
+            g.fpx = q.sg * F;
+            g.fpy = (R)0;
         }
         return g;
     }
@@ -499,6 +561,37 @@ struct Marcher {
         a.flush(row(ROW_JR), st, (GEOM == WK_CYL && WARM) ? -1 : ROW_M3 - ROW_JR);
     }
 
+    // ---- exchange between the workgroups of a group -------------------------
+    // Sum the deposit rows [r0, r0 + nr) over the G workgroups, in rank order,
+    // into every workgroup's LDS rows.  Every thread calls it (it contains the
+    // barriers); the caller synchronizes afterwards.
+    __device__ __forceinline__ void exchange(int r0, int nr)
+    {
+        if (grp.G <= 1) return;
+        __syncthreads();                       // this workgroup's deposits are complete
+        const int64_t part = (int64_t)kXRows * st;
+        double* mine = grp.xbuf + (int64_t)grp.g * part;
+        const int items = nr * N1;
+        for (int it = tid; it < items; it += T) {
+            const int r = r0 + it / N1, j = it % N1;
+            st_dev(mine + (int64_t)r * st + j, row(r)[j]);
+        }
+        group_barrier(grp);
+        const int G = grp.G;
+        for (int it = tid; it < items; it += T) {
+            const int r = r0 + it / N1, j = it % N1;
+            const double* src = grp.xbuf + (int64_t)r * st + j;
+            double v[kMaxGroup];
+#pragma unroll
+            for (int q = 0; q < kMaxGroup; ++q) v[q] = q < G ? ld_dev(src + q * part) : 0.0;
+            double s = v[0];
+#pragma unroll
+            for (int q = 1; q < kMaxGroup; ++q)
+                if (q < G) s += v[q];
+            row(r)[j] = s;
+        }
+    }
+
     // ---- solves ----------------------------------------------------------------
     // 1 / V_j of the hat volumes.
     __device__ __forceinline__ double inv_volume(int j) const
@@ -528,8 +621,9 @@ struct Marcher {
         const double incl = wave_prefix(s);
         if (lane == 63) wt[wid] = incl;
         sync();
-        const int W = T >> 6;
+        constexpr int W = T >> 6;
         double before = 0.0, tot = 0.0;
+#pragma unroll
         for (int w = 0; w < W; ++w) {
             const double v = wt[w];
             if (w < wid) before += v;
@@ -579,7 +673,8 @@ struct Marcher {
     }
 
     // All threads: divide the deposits by the node volumes, add the beam
-    // current; and the node derivative psi' of this stage's psi.
+    // current (when given as a row); and the node derivative psi' of this
+    // stage's psi.
     __device__ __forceinline__ void finalize_moments(const double* jb_row)
     {
         const double* psi = row(ROW_PSI2);
@@ -588,7 +683,7 @@ struct Marcher {
         for (int j = tid; j < N1; j += T) {
             const double iv = inv_volume(j);
             for (int r = ROW_JR; r <= ROW_M5; ++r) row(r)[j] = row(r)[j] * iv;
-            row(ROW_JZ)[j] += jb_row[j];
+            if (jb_row) row(ROW_JZ)[j] += jb_row[j];
             double v;
             if (j == 0) v = 0.0;
             else if (j == N) v = (psi[N] - psi[N - 1]) * ih;
@@ -664,38 +759,39 @@ struct Marcher {
             for (int r = ROW_S; r <= ROW_M5; ++r) row(r)[j] = 0.0;
     }
 
+    // The fields of slice k (one workgroup of a group writes them, with
+    // device-coherent stores so that other compute units may read them during
+    // the launch).
     __device__ __forceinline__ void store_fields(int k, const double* psi, const double* ez, const double* bt,
-                                 const double* dpsi)
+                                                 const double* dpsi)
     {
+        if (!stores) return;
         R* f = (R*)d.fields;
         const int64_t plane = (int64_t)d.n_xi * N1;
         unsigned long long bad = 0;
         for (int j = tid; j < N1; j += T) {
             const double v0 = psi[j], v1 = ez[j], v2 = bt[j], v3 = -dpsi[j];
             const int64_t o = (int64_t)k * N1 + j;
-            f[o] = (R)v0;
-            f[plane + o] = (R)v1;
-            f[2 * plane + o] = (R)v2;
-            f[3 * plane + o] = (R)v3;
+            st_dev(f + o, (R)v0);
+            st_dev(f + plane + o, (R)v1);
+            st_dev(f + 2 * plane + o, (R)v2);
+            st_dev(f + 3 * plane + o, (R)v3);
             bad += !isfinite(v0) + !isfinite(v1) + !isfinite(v2) + !isfinite(v3);
         }
         if (bad) atomicAdd(d.counters + WK_CNT_NONFINITE, bad);
     }
 
     // ---- particle passes ----------------------------------------------------
-    // Run fn(m, part) over this thread's particles; with RESIDENT the
-    // particles live in P[], otherwise each tile is loaded (and stored when
-    // STORE) around the call.
     // Block of K particles owned by this thread within a tile.  When whole
     // blocks tile the cells (K divides ppc and the waves cover the blocks of a
     // cell evenly), consecutive lanes take consecutive cells so that their
     // deposits land on different LDS banks.
     __device__ __forceinline__ int block_of(int t) const
     {
-        const int ppc = (int)(d.np / N);
+        const int ppc = d.ppc;
         if (kr > 0 && ppc % kr == 0) {
             const int hpc = ppc / kr;
-            const int W = T >> 6;
+            constexpr int W = T >> 6;
             if (hpc > 1 && W % hpc == 0) {
                 const int l = t & 63, w = t >> 6;
                 return l * hpc + (w % hpc) + (w / hpc) * 64 * hpc;
@@ -704,22 +800,37 @@ struct Marcher {
         return t;
     }
 
+    // Resident particle m of this thread (registers; D0 and w in registers or
+    // LDS slots).
+    __device__ __forceinline__ Part<R> resident(int m) const
+    {
+        Part<R> p;
+        p.x = X[m];
+        p.y = Y[m];
+        p.px = PX[m];
+        p.py = PY[m];
+        if (kRegConst) {
+            p.d0 = D0r[m];
+            p.w = Wr[m];
+        } else {
+            p.d0 = cd0[m * T + tid];
+            p.w = cw[m * T + tid];
+        }
+        return p;
+    }
+
+    // Run fn(m, part) over this thread's particles (m: resident slot, or -1
+    // when streamed); with STORE the (possibly modified) state is kept.
     template <bool STORE, typename Fn>
     __device__ __forceinline__ void for_parts(Fn fn)
     {
-        if (RESIDENT) {
+        if (RES) {
             const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (m < kr && i0 + m < d.np) {
-                    Part<R> p;
-                    p.x = X[m];
-                    p.y = Y[m];
-                    p.px = PX[m];
-                    p.py = PY[m];
-                    p.d0 = cd0[m * nt() + tid];
-                    p.w = cw[m * nt() + tid];
-                    fn(p);
+                    Part<R> p = resident(m);
+                    fn(m, p);
                     if (STORE) {
                         X[m] = p.x;
                         Y[m] = p.y;
@@ -737,7 +848,7 @@ struct Marcher {
                     const int64_t i = i0 + m;
                     if (i < d.np) {
                         Part<R> p = load(i);
-                        fn(p);
+                        fn(-1, p);
                         if (STORE) store_state(i, p);
                     }
                 }
@@ -751,6 +862,8 @@ struct Marcher {
     struct NoRecord {
         __device__ __forceinline__ void before_b(Marcher&, int, int) {}
         __device__ __forceinline__ void after_b(Marcher&, int, int, const double*) {}
+        // extra raw J_z deposits (before the exchange) at slice k
+        __device__ __forceinline__ void deposit_beam(Marcher&, int) {}
     };
 
     // Run fn(i, part) over this thread's particles (read only), i the
@@ -758,21 +871,11 @@ struct Marcher {
     template <typename Fn>
     __device__ __forceinline__ void for_idx(Fn fn)
     {
-        if (RESIDENT) {
+        if (RES) {
             const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
-            for (int m = 0; m < K; ++m) {
-                if (m < kr && i0 + m < d.np) {
-                    Part<R> p;
-                    p.x = X[m];
-                    p.y = Y[m];
-                    p.px = PX[m];
-                    p.py = PY[m];
-                    p.d0 = cd0[m * nt() + tid];
-                    p.w = cw[m * nt() + tid];
-                    fn(i0 + m, p);
-                }
-            }
+            for (int m = 0; m < K; ++m)
+                if (m < kr && i0 + m < d.np) fn(i0 + m, resident(m));
         } else {
             const int64_t per_tile = (int64_t)T * K;
             for (int64_t base = 0; base < d.np; base += per_tile) {
@@ -799,6 +902,35 @@ struct Marcher {
         run(hooks);
     }
 
+    // The stage-1 derivative f_k of a particle: cached in registers for
+    // resident particles (computed once per slice), else recomputed.
+    template <bool FILL>
+    __device__ __forceinline__ Deriv<R> fk(int m, const Part<R>& p, const double* psi1, const double* dpsi1,
+                                           const double* b1)
+    {
+        if (kCacheF && m >= 0) {
+            if (FILL) {
+                const Deriv<R> g = derivative(p, psi1, dpsi1, b1);
+#pragma unroll
+                for (int q = 0; q < K; ++q)
+                    if (q == m) {
+                        FX[q] = g.fx;
+                        FY[q] = g.fy;
+                        FPX[q] = g.fpx;
+                        FPY[q] = g.fpy;
+                    }
+                return g;
+            }
+            Deriv<R> g;
+            g.fx = FX[m];
+            g.fy = FY[m];
+            g.fpx = FPX[m];
+            g.fpy = FPY[m];
+            return g;
+        }
+        return derivative(p, psi1, dpsi1, b1);
+    }
+
     template <class Hooks>
     __device__ __forceinline__ void run(Hooks& hooks)
     {
@@ -816,7 +948,7 @@ struct Marcher {
             for (int r = ROW_S; r <= ROW_M5; ++r) row(r)[j] = 0.0;
         }
         blk = block_of(tid);
-        if (RESIDENT) {
+        if (RES) {
             const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
@@ -826,9 +958,12 @@ struct Marcher {
                 Y[m] = p.y;
                 PX[m] = p.px;
                 PY[m] = p.py;
-                if (m < kr) {
-                    cd0[m * nt() + tid] = p.d0;
-                    cw[m * nt() + tid] = p.w;
+                if (kRegConst) {
+                    D0r[m] = p.d0;
+                    Wr[m] = p.w;
+                } else if (m < kr) {
+                    cd0[m * T + tid] = p.d0;
+                    cw[m * T + tid] = p.w;
                 }
             }
         }
@@ -836,9 +971,10 @@ struct Marcher {
         {
             Acc<R, 1> a;
             a.reset(-1);
-            for_parts<false>([&](Part<R>& p) { dep_S(a, p); });
+            for_parts<false>([&](int, Part<R>& p) { dep_S(a, p); });
             a.flush(row(ROW_S), st);
         }
+        exchange(ROW_S, 1);
         for (int k = 0; k < d.n_xi; ++k) {
             hooks.before_slice(*this, k);
             const double* jb0 = hooks.jb_row(*this, k);
@@ -849,9 +985,11 @@ struct Marcher {
             {
                 Acc<R, 7> a;
                 a.reset(-1);
-                for_parts<false>([&](Part<R>& p) { dep_moments(a, p); });
+                for_parts<false>([&](int, Part<R>& p) { dep_moments(a, p); });
                 flush_moments(a);
             }
+            hooks.deposit_beam(*this, k);
+            exchange(ROW_JR, ROW_M5 - ROW_JR + 1);
             sync();
             finalize_moments(jb0);
             sync();
@@ -860,7 +998,7 @@ struct Marcher {
             hooks.before_b(*this, k, 0);
             solve_b(dpsi2, ez, b1);
             hooks.after_b(*this, k, 0, b1);
-            // keep the stage-1 psi, psi' for the derivative recomputed later
+            // keep the stage-1 psi, psi' for the derivative
             sync();
             for (int j = tid; j < N1; j += T) {
                 psi1[j] = psi2[j];
@@ -874,22 +1012,25 @@ struct Marcher {
             {
                 Acc<R, 1> a;
                 a.reset(-1);
-                for_parts<false>([&](Part<R>& p) {
-                    dep_S(a, advance(p, derivative(p, psi1, dpsi1, b1), dxi));
+                for_parts<false>([&](int m, Part<R>& p) {
+                    dep_S(a, advance(p, fk<true>(m, p, psi1, dpsi1, b1), dxi));
                 });
                 a.flush(row(ROW_S), st);
             }
+            exchange(ROW_S, 1);
             sync();
             solve_psi(psi2);
             sync();
             {
                 Acc<R, 7> a;
                 a.reset(-1);
-                for_parts<false>([&](Part<R>& p) {
-                    dep_moments(a, advance(p, derivative(p, psi1, dpsi1, b1), dxi));
+                for_parts<false>([&](int m, Part<R>& p) {
+                    dep_moments(a, advance(p, fk<false>(m, p, psi1, dpsi1, b1), dxi));
                 });
                 flush_moments(a);
             }
+            hooks.deposit_beam(*this, k + 1);
+            exchange(ROW_JR, ROW_M5 - ROW_JR + 1);
             sync();
             finalize_moments(hooks.jb_row(*this, k + 1));
             sync();
@@ -903,39 +1044,32 @@ struct Marcher {
             {
                 Acc<R, 1> a;
                 a.reset(-1);
-                for_parts<true>([&](Part<R>& p) {
-                    const Deriv g0 = derivative(p, psi1, dpsi1, b1);
-                    const Deriv g1 = derivative(advance(p, g0, dxi), psi2, dpsi2, b2);
-                    p.x = p.x + hd * (g0.fx + g1.fx);
-                    p.px = p.px + hd * (g0.fpx + g1.fpx);
+                for_parts<true>([&](int m, Part<R>& p) {
+                    const Deriv<R> g0 = fk<false>(m, p, psi1, dpsi1, b1);
+                    const Deriv<R> g1 = derivative(advance(p, g0, dxi), psi2, dpsi2, b2);
+                    p.x = p.x + hd * ((double)g0.fx + (double)g1.fx);
+                    p.px = p.px + hd * ((double)g0.fpx + (double)g1.fpx);
                     if (GEOM == WK_CYL && WARM) {
-                        p.y = p.y + hd * (g0.fy + g1.fy);
-                        p.py = p.py + hd * (g0.fpy + g1.fpy);
+                        p.y = p.y + hd * ((double)g0.fy + (double)g1.fy);
+                        p.py = p.py + hd * ((double)g0.fpy + (double)g1.fpy);
                     }
                     reflect(p);
                     dep_S(a, p);
                 });
                 a.flush(row(ROW_S), st);
             }
+            exchange(ROW_S, 1);
         }
-        if (RESIDENT) {
+        if (RES && keep_state) {
             const int64_t i0 = (int64_t)blk * kr;
 #pragma unroll
             for (int m = 0; m < K; ++m)
-                if (m < kr && i0 + m < d.np) {
-                    Part<R> p;
-                    p.x = X[m];
-                    p.y = Y[m];
-                    p.px = PX[m];
-                    p.py = PY[m];
-                    store_state(i0 + m, p);
-                }
+                if (m < kr && i0 + m < d.np) store_state(i0 + m, resident(m));
         }
         if (clamps) atomicAdd(d.counters + WK_CNT_D_CLAMP, clamps);
         if (walls) atomicAdd(d.counters + WK_CNT_WALL, walls);
     }
 };
-
 
 }  // namespace dev
 }  // namespace wk

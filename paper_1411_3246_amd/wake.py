@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libwake.so")
 WK_CYL, WK_SLAB = 0, 1
 WK_FP64, WK_MIXED = 0, 1
 COUNTER_NAMES = ["d_clamp", "wall", "nonfinite", "beam_out_deposit", "beam_out_push", "beam_bin",
-                 "pipeline_abort"]
+                 "pipeline_abort", "beam_order"]
 NCOUNTERS = 8
 
 
@@ -67,13 +67,13 @@ EXPORTS = [
     "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
-    "wk_cycle_workspace_size", "wk_cycle",
+    "wk_cycle_workspace_size", "wk_cycle", "wk_plan_set_group", "wk_plan_group", "wk_cycle_group",
     "wk_gradient_workspace_size", "wk_gradient_forward", "wk_gradient_backward",
 ]
 
 _NON_STATUS = {"wk_version", "wk_status_string", "wk_last_error", "wk_plan_destroy",
                "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size",
-               "wk_cycle_workspace_size", "wk_gradient_workspace_size"}
+               "wk_cycle_workspace_size", "wk_gradient_workspace_size", "wk_plan_group", "wk_cycle_group"}
 
 _lib = None
 
@@ -99,6 +99,11 @@ def lib():
     L.wk_plan_set_threads.argtypes = [vp, i32]
     L.wk_plan_threads.argtypes = [vp]
     L.wk_plan_threads.restype = i32
+    L.wk_plan_set_group.argtypes = [vp, i32]
+    L.wk_plan_group.argtypes = [vp]
+    L.wk_plan_group.restype = i32
+    L.wk_cycle_group.argtypes = [vp, i32]
+    L.wk_cycle_group.restype = i32
     L.wk_counters_zero.argtypes = [vp, vp]
     L.wk_counters_read.argtypes = [vp, vp, vp]
     L.wk_init_plasma.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp]
@@ -170,7 +175,7 @@ def problem_struct(p: inputs.Problem) -> WkProblem:
 class Plan:
     """A validated problem and its launch shape (host-only)."""
 
-    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None):
+    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None, group: Optional[int] = None):
         self.problem = problem
         self._s = problem_struct(problem)
         h = C.c_void_p()
@@ -178,6 +183,8 @@ class Plan:
         self.handle = h
         if threads is not None:
             _check(lib().wk_plan_set_threads(self.handle, threads), "wk_plan_set_threads")
+        if group is not None:
+            _check(lib().wk_plan_set_group(self.handle, group), "wk_plan_set_group")
         sz = WkSizes()
         _check(lib().wk_plan_sizes(self.handle, C.byref(sz)), "wk_plan_sizes")
         self.sizes = sz
@@ -190,6 +197,18 @@ class Plan:
     @property
     def threads(self) -> int:
         return lib().wk_plan_threads(self.handle)
+
+    @property
+    def group(self) -> int:
+        """Workgroups that march one response of wk_plasma_response."""
+        return lib().wk_plan_group(self.handle)
+
+    def set_group(self, group: int):
+        _check(lib().wk_plan_set_group(self.handle, group), "wk_plan_set_group")
+
+    def cycle_group(self, n_steps: int) -> int:
+        """Workgroups per response that wk_cycle uses for n_steps steps."""
+        return lib().wk_cycle_group(self.handle, n_steps)
 
     @property
     def real_dtype(self):
@@ -369,10 +388,11 @@ class Simulation:
     """Buffers and calls of one problem: plasma response for the frozen beam,
     then the beam advanced over dt (Section II A of the WAKE paper)."""
 
-    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None, device="cuda"):
+    def __init__(self, problem: inputs.Problem, threads: Optional[int] = None, device="cuda",
+                 group: Optional[int] = None):
         import torch
         self.problem = problem
-        self.plan = Plan(problem, threads)
+        self.plan = Plan(problem, threads, group)
         self.device = device
         self.plasma = self.plan.alloc_plasma(device)
         self.fields = self.plan.alloc_fields(device)
