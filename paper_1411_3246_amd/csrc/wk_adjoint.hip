@@ -41,6 +41,7 @@ __device__ __forceinline__ const double* tape_rows(const double* tape, int k, in
 // ---------------------------------------------------------------------------
 template <class M>
 struct RecordHooks : M::NoRecord {
+    static constexpr bool kKeepMoments = true;   // the tape holds the moment rows
     double* tape;
     double* ckpt;
     int every;

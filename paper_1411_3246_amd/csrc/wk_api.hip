@@ -101,9 +101,10 @@ int64_t member_np(const wk_plan* pl, int G) { return (int64_t)((pl->N + G - 1) /
 // March region at the start of a plan workspace: the large-grid node rows of
 // up to kMaxGroup workgroups, the group's partial rows and its counter.
 size_t march_grow_bytes(const wk_plan* pl) { return pl->big ? wk::kMaxGroup * a256(wk::big_rows_bytes(pl->N1)) : 0; }
+// exchange rows of a group: two slots of G partials of kXRows node rows
 size_t march_xbuf_bytes(int N1, int G)
 {
-    return a256((size_t)G * wk::kXRows * wk::lds_stride(N1) * sizeof(double));
+    return a256((size_t)2 * G * wk::kXRows * wk::lds_stride(N1) * sizeof(double));
 }
 size_t march_region_bytes(const wk_plan* pl) { return march_grow_bytes(pl) + march_xbuf_bytes(pl->N1, wk::kMaxGroup) + 256; }
 
@@ -354,7 +355,7 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     wk_status st = check_plasma(plan, plasma);
     if (st != WK_OK) return st;
     const int G = single_group(plan);
-    const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec);
+    const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec, G);
     char* ws = (char*)d_workspace;
     wk::MarchLaunch L{};
     L.one = make_desc(plan, plasma, d_jb, d_fields, d_counters);
@@ -364,7 +365,10 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     L.grow = plan->big ? (double*)ws : nullptr;
     L.grow_stride = wk::lds_stride(plan->N1);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = wk::launch_zero_u32(L.one.gctr, 1, s);
+    // the exchange slots start zeroed (tag 0) for every launch
+    hipError_t e = G > 1 ? wk::launch_zero_u32((unsigned*)L.one.xbuf, (int64_t)march_xbuf_bytes(plan->N1, G) / 4, s)
+                         : hipSuccess;
+    if (e == hipSuccess) e = wk::launch_zero_u32(L.one.gctr, 1, s);
     if (e == hipSuccess)
         e = wk::launch_march(L, plan->p.prec, plan->p.geom, L.one.warm, shape, G, plan->N1, s);
     return hip_status(e, "plasma response");
@@ -502,14 +506,17 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
     bool warm = false;
     for (int i = 0; i < n; ++i) warm |= h_plans[i]->p.u_th > 0.0;
     const int prec = h_plans[0]->p.prec, geom = h_plans[0]->p.geom;
-    const int shape = wk::pick_shape(B.max_member, threads > 0 ? threads : 512, B.max_nodes, prec);
+    int gmax = 1;
+    for (int i = 0; i < n; ++i) gmax = std::max(gmax, B.group[i]);
+    const int shape = wk::pick_shape(B.max_member, threads > 0 ? threads : 512, B.max_nodes, prec, gmax);
     const int occ = wk::march_occupancy(prec, geom, warm ? 1 : 0, shape, B.max_nodes);
     if (occ <= 0) return fail(WK_ERR_UNSUPPORTED, "batch: no resident workgroup fits (%d nodes)", B.max_nodes);
     const int per_cu = wg_per_cu > 0 ? std::min<int>(wg_per_cu, occ) : occ;
     const int grid = std::min(B.tickets, device_cus() * per_cu);
     hipStream_t s = (hipStream_t)stream;
-    // ticket counter and group counters start at zero (a kernel: capturable)
-    hipError_t e = wk::launch_zero_u32((unsigned*)d_workspace, (int64_t)(256 + (size_t)n * wk::kCtrPad * 4) / 4, s);
+    // ticket counter, group counters and exchange slots start at zero (a
+    // kernel: capturable)
+    hipError_t e = wk::launch_zero_u32((unsigned*)d_workspace, (int64_t)B.ws / 4, s);
     if (e != hipSuccess) return hip_status(e, "batch queue");
     wk::MarchLaunch L{};
     L.descs = (const wk::MarchDesc*)d_desc;
@@ -543,11 +550,18 @@ CycleLayout cycle_layout(const wk_plan* pl, int32_t n_steps)
     CycleLayout L;
     const int prec = pl->p.prec, geom = pl->p.geom, warm = pl->p.u_th > 0.0 ? 1 : 0;
     const int cus = device_cus();
-    const int gmax = std::min(wk::kMaxGroup, pl->N);
+    // beyond 8 workgroups the exchanges cost more than the split saves
+    const int gmax = std::min(pl->group > 0 ? wk::kMaxGroup : 8, pl->N);
     bool found = false;
     for (int G = gmax; G >= 1 && !found; --G) {
         if (pl->group > 0 && G != pl->group) continue;
-        const int shape = wk::pick_shape(member_np(pl, G), pl->threads, pl->N1, prec);
+        int shape = wk::pick_shape(member_np(pl, G), pl->threads, pl->N1, prec, G);
+        // the ring of beam-current rows may push a grid into the large-grid shapes
+        if (!wk::kShapes[shape].big && !wk::lds_fits(wk::cycle_lds_bytes(shape, pl->N1, prec)))
+            shape = (prec != WK_FP64 && member_np(pl, G) <= (int64_t)wk::kShapes[wk::SH_BIG_512_8].threads *
+                                                              wk::kShapes[wk::SH_BIG_512_8].kp)
+                        ? wk::SH_BIG_512_8
+                        : wk::SH_BIG_STREAM;
         int occ = wk::cycle_occupancy(prec, geom, warm, shape, pl->N1);
         if (occ <= 0) occ = 1;
         const int cap = (cus * occ / G) * G;
@@ -614,6 +628,8 @@ wk_status wk_cycle(const wk_plan* plan, const wk_plasma_bufs* plasma, const wk_b
     char* ws = (char*)d_workspace;
     const wk::GridDesc g = grid_of(plan);
     hipError_t e = wk::launch_zero_u32((unsigned*)(ws + L.progress), (int64_t)(L.zero_end - L.progress) / 4, s);
+    // the exchange slots start zeroed (tag 0)
+    if (e == hipSuccess && L.G > 1) e = wk::launch_zero_u32((unsigned*)(ws + L.xbuf), (int64_t)(L.total - L.xbuf) / 4, s);
     if (e != hipSuccess) return hip_status(e, "cycle init");
     e = wk::launch_beam_bins_split(g, plan->p.n_beam, L.G, *beam, (unsigned*)(ws + L.count), (unsigned*)(ws + L.start),
                                    (unsigned*)(ws + L.fill), (unsigned*)(ws + L.order), s);

@@ -33,6 +33,7 @@ using dev::st_dev;
 
 constexpr int kLag = 2;   // slices of response n-1 needed beyond a bin: a particle of
                           // bin b gathers slices b and b+1
+constexpr int kRing = kCycleRing;  // LDS rows of beam current in flight (grids whose rows fit LDS)
 
 // One beam subset (pointers offset to its first particle).
 struct BeamSub {
@@ -87,6 +88,8 @@ struct CycleHooks : M::NoRecord {
     const R* prev;         // fields of response n-1 (ring slot)
     BeamSub B;
     int* wtot;             // LDS scratch of the compaction
+    double* ring;          // kRing LDS rows of raw beam J_z (row k at k % kRing); null on large grids
+    int st;                // stride of the ring rows
     unsigned seen;         // last progress[n-1] read (thread 0)
     unsigned pos;          // next free entry of the new order (uniform)
     // this subset's bins before this response's push (read) and after it (written)
@@ -96,8 +99,10 @@ struct CycleHooks : M::NoRecord {
     unsigned* out_order;
     unsigned long long out_push, out_dep, bad_bin;
 
-    __device__ __forceinline__ CycleHooks(const CycleDesc& cd, int resp, int rank, int* wt)
-        : c(cd), n(resp), g(rank), next_bin(0), wtot(wt), seen(0), pos(0), out_push(0), out_dep(0), bad_bin(0)
+    __device__ __forceinline__ CycleHooks(const CycleDesc& cd, int resp, int rank, int* wt, double* ring_rows,
+                                          int stride)
+        : c(cd), n(resp), g(rank), next_bin(0), wtot(wt), ring(ring_rows), st(stride), seen(0), pos(0),
+          out_push(0), out_dep(0), bad_bin(0)
     {
         const int G = c.base.group;
         prev = n > 0 ? (const R*)c.ring + (int64_t)((n - 1) & 1) * c.slot_elems : nullptr;
@@ -180,7 +185,11 @@ struct CycleHooks : M::NoRecord {
                 if (kk != nxi && kk != b && kk != b + 1) ++bad_bin;   // moved by more than a slice
             }
             const double r = dev::beam_radius(gr, x, y);
-            if (r > gr.r_max || xi < gr.xi_min || xi >= xi_max) ++out_dep;
+            if (r > gr.r_max || xi < gr.xi_min || xi >= xi_max) {
+                ++out_dep;
+                continue;
+            }
+            if (ring) ring_deposit(r, xi, B.w[i], b);
         }
         dev::wait_vm();
         __syncthreads();
@@ -195,12 +204,44 @@ struct CycleHooks : M::NoRecord {
         return b + 1 < next_bin ? ld_dev(out_start + b + 1) : pos;
     }
 
-    // Raw J_z of the beam particles of this subset at slice k (Section II A:
-    // the total current includes the beam's; v_z = c): the particles of new
-    // bins k-1 and k, bilinear in (r, xi); divided by the node volumes with
-    // the plasma deposits.
+    // Raw J_z of one beam particle of bin b (just pushed) into the ring rows
+    // of slices kk and kk + 1, bilinear in (r, xi) (Section II A: the total
+    // current includes the beam's; v_z = c).  A particle of bin b is at
+    // kk = b or b + 1; rows b .. b + 2 are free or still accumulating.
+    __device__ __forceinline__ void ring_deposit(double r, double xi, double w, int b)
+    {
+        const GridDesc& gr = c.grid;
+        const double u = (xi - gr.xi_min) / gr.dxi;
+        int kk = (int)floor(u);
+        if (kk > gr.n_xi - 1) kk = gr.n_xi - 1;
+        if (kk < b || kk > b + 1) return;   // counted as a bin escape after the push
+        const double tk = u - kk;
+        int j;
+        double tr;
+        dev::grid_hat(gr, r, j, tr);
+        const double v = -w / gr.dxi;
+        double* r0 = ring + (kk % kRing) * st;
+        atomicAdd(r0 + j, v * (1.0 - tr) * (1.0 - tk));
+        atomicAdd(r0 + j + 1, v * tr * (1.0 - tk));
+        if (kk + 1 < gr.n_xi) {
+            double* r1 = ring + ((kk + 1) % kRing) * st;
+            atomicAdd(r1 + j, v * (1.0 - tr) * tk);
+            atomicAdd(r1 + j + 1, v * tr * tk);
+        }
+    }
+
+    // Raw J_z of the beam particles of this subset at slice k, added to the
+    // J_z deposit row (divided by the node volumes with the plasma deposits):
+    // the ring row of slice k, or on large grids the particles of new bins
+    // k-1 and k, bilinear in (r, xi).
     __device__ __forceinline__ void deposit_beam(M& m, int k)
     {
+        if (ring) {
+            double* jz = m.row(ROW_JZ);
+            const double* rk = ring + (k % kRing) * st;
+            for (int j = threadIdx.x; j <= c.grid.n_r; j += T) atomicAdd(jz + j, rk[j]);
+            return;
+        }
         if (B.n == 0) return;
         const GridDesc& gr = c.grid;
         const unsigned* S = n > 0 ? out_start : in_start;
@@ -279,6 +320,11 @@ struct CycleHooks : M::NoRecord {
 
     __device__ __forceinline__ void after_store(M&, int k)
     {
+        // ring row k is used up: cleared for slice k + kRing
+        if (ring) {
+            double* rk = ring + (k % kRing) * st;
+            for (int j = threadIdx.x; j <= c.grid.n_r; j += T) rk[j] = 0.0;
+        }
         if (g != 0) return;
         dev::wait_vm();
         __syncthreads();
@@ -307,8 +353,8 @@ __device__ __forceinline__ void push_bin_only(const CycleDesc& c, const BeamSub&
     }
 }
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
-__global__ __launch_bounds__(T) void k_cycle(CycleDesc c)
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS>
+__global__ __launch_bounds__(T, WPS) void k_cycle(CycleDesc c)
 {
     extern __shared__ double smem[];
     __shared__ int s_ticket;
@@ -356,13 +402,18 @@ __global__ __launch_bounds__(T) void k_cycle(CycleDesc c)
             dev::Group grp;
             grp.G = G;
             grp.g = g;
-            grp.xbuf = c.xbuf ? c.xbuf + (int64_t)n * G * kXRows * st : nullptr;
+            grp.xbuf = c.xbuf ? c.xbuf + (int64_t)n * 2 * G * kXRows * st : nullptr;
             grp.ctr = c.gctr ? c.gctr + (int64_t)n * kCtrPad : nullptr;
             grp.abort = c.abort_flag;
-            void* pconst = BIG ? nullptr : (void*)(smem + NUM_ROWS * st);
+            double* ring = BIG ? nullptr : smem + NUM_ROWS * st;
+            void* pconst = BIG ? nullptr : (void*)(smem + (NUM_ROWS + kRing) * st);
+            if (ring) {
+                for (int q = threadIdx.x; q < kRing * st; q += T) ring[q] = 0.0;
+                __syncthreads();
+            }
             // resident particles are loaded from the template and not stored back
             M m(d, smem, pconst, grp, g == 0, false);
-            CycleHooks<R, M> hooks(c, n, g, wtot);
+            CycleHooks<R, M> hooks(c, n, g, wtot, ring, st);
             m.run(hooks);
             hooks.finish();
             out_push = hooks.out_push;
@@ -406,7 +457,7 @@ hipError_t go(const CycleDesc& c, int grid, size_t lds, hipStream_t s, int* occ)
     if constexpr (S.big && S.resident && sizeof(R) == 8) {
         return hipErrorInvalidValue;
     } else {
-        auto kern = k_cycle<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big>;
+        auto kern = k_cycle<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd>;
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, S.threads, lds);
@@ -420,11 +471,12 @@ hipError_t go_shape(const CycleDesc& c, int shape, int grid, size_t lds, hipStre
 {
     switch (shape) {
     case SH_256_4: return go<R, GEOM, WARM, SH_256_4>(c, grid, lds, s, occ);
+    case SH_512_8: return go<R, GEOM, WARM, SH_512_8>(c, grid, lds, s, occ);
     case SH_512_4: return go<R, GEOM, WARM, SH_512_4>(c, grid, lds, s, occ);
     case SH_512_16: return go<R, GEOM, WARM, SH_512_16>(c, grid, lds, s, occ);
     case SH_1024_8: return go<R, GEOM, WARM, SH_1024_8>(c, grid, lds, s, occ);
     case SH_1024_STREAM: return go<R, GEOM, WARM, SH_1024_STREAM>(c, grid, lds, s, occ);
-    case SH_BIG_1024_8: return go<R, GEOM, WARM, SH_BIG_1024_8>(c, grid, lds, s, occ);
+    case SH_BIG_512_8: return go<R, GEOM, WARM, SH_BIG_512_8>(c, grid, lds, s, occ);
     case SH_BIG_STREAM: return go<R, GEOM, WARM, SH_BIG_STREAM>(c, grid, lds, s, occ);
     default: return hipErrorInvalidValue;
     }

@@ -33,7 +33,7 @@ struct MarchDesc {
     double* grow;        // large grids: global node rows, BIG_ROWS x stride doubles per workgroup
     int32_t ppc;         // macroparticles per cell
     int32_t group;       // workgroups that march this response together (1..kMaxGroup)
-    double* xbuf;        // group > 1: partial deposit rows, [group][kXRows][stride] doubles
+    double* xbuf;        // group > 1: partial deposit rows, [2][group][kXRows][stride] doubles (zeroed)
     unsigned int* gctr;  // group > 1: arrival counter of the group barrier (own 256-byte line)
 };
 
@@ -73,13 +73,23 @@ inline size_t march_lds_bytes(int n_nodes, int /*threads*/)
 struct ShapeInfo {
     int threads, kp;
     bool resident, big;
+    int waves_per_simd;   // occupancy the kernel is compiled for (registers)
 };
 enum ShapeId {
-    SH_256_4 = 0, SH_512_4, SH_512_16, SH_1024_8, SH_1024_STREAM, SH_BIG_1024_8, SH_BIG_STREAM, NUM_SHAPES
+    SH_256_4 = 0, SH_512_4, SH_512_8, SH_512_16, SH_1024_8, SH_1024_STREAM, SH_BIG_512_8, SH_BIG_STREAM, NUM_SHAPES
 };
+// The 256-thread shape is compiled for two workgroups per compute unit, so
+// that one workgroup's field solves and particle passes run while the other
+// waits at a group exchange.
+// Large grids use 512 threads: their node rows take most of the LDS, and
+// the 256-register budget of 512-thread workgroups keeps their kernels
+// free of heavy spilling.
+// The 16-particle shape marches single workgroups only (group 1): it is
+// compiled without the group exchange, which it could not afford in
+// registers.
 constexpr ShapeInfo kShapes[NUM_SHAPES] = {
-    {256, 4, true, false}, {512, 4, true, false}, {512, 16, true, false}, {1024, 8, true, false},
-    {1024, 8, false, false}, {1024, 8, true, true}, {1024, 8, false, true},
+    {256, 4, true, false, 2}, {512, 4, true, false, 2}, {512, 8, true, false, 2}, {512, 16, true, false, 2},
+    {1024, 8, true, false, 4}, {1024, 8, false, false, 4}, {512, 8, true, true, 2}, {512, 8, false, true, 2},
 };
 // LDS bytes of a shape for grids of up to n_nodes nodes (rows, plus the
 // resident D0 / w slots when they are not kept in registers).
@@ -88,8 +98,9 @@ size_t shape_lds_bytes(int shape, int n_nodes, int prec);
 bool march_needs_global_rows(int n_nodes);
 // The shape for `np` particles per workgroup on a grid of n_nodes nodes: the
 // smallest resident shape of at least `threads` threads that holds them and
-// fits LDS, else a streamed one.
-int pick_shape(int64_t np, int threads, int n_nodes, int prec);
+// fits LDS (for a group of more than one workgroup, one with the exchange),
+// else a streamed one.
+int pick_shape(int64_t np, int threads, int n_nodes, int prec, int group);
 
 // One launch of the march kernel: a single response (descs == nullptr; its
 // `group` workgroups are the grid) or a batch (workgroups take tickets; each
@@ -158,13 +169,19 @@ struct CycleDesc {
     unsigned long long* abort_flag;  // counter slot, zeroed
     double* plasma_ws;               // streamed particles: grid * 4 * (largest subset) doubles
     double* big_rows;                // large grids: grid * BIG_ROWS node rows
-    double* xbuf;                    // group > 1: [n_steps + 1][group][kXRows][stride] doubles
+    double* xbuf;                    // group > 1: [n_steps][2][group][kXRows][stride] doubles (zeroed)
     unsigned int* gctr;              // group > 1: [n_steps + 1] counters, kCtrPad apart (zeroed)
     void* ring;                      // 2 field slots
     int64_t slot_elems;
     int n_steps;
     double dt;
 };
+// Rows of beam current the cycle keeps in LDS (grids whose rows fit LDS).
+constexpr int kCycleRing = 4;
+// LDS bytes of the cycle kernel of a shape (the march rows plus the ring).
+size_t cycle_lds_bytes(int shape, int n_nodes, int prec);
+// true when `bytes` of dynamic LDS fit one workgroup
+bool lds_fits(size_t bytes);
 hipError_t launch_cycle(const CycleDesc& c, int prec, int shape, int grid, hipStream_t s);
 int cycle_occupancy(int prec, int geom, int warm, int shape, int n_nodes);
 // Bin each of `group` contiguous beam subsets by xi cell: bin_start gets

@@ -31,16 +31,17 @@ size_t shape_lds_bytes(int shape, int n_nodes, int prec)
     return lds;
 }
 
-int pick_shape(int64_t np, int threads, int n_nodes, int prec)
+int pick_shape(int64_t np, int threads, int n_nodes, int prec, int group)
 {
     if (march_needs_global_rows(n_nodes))
-        return (prec != WK_FP64 && np <= (int64_t)kShapes[SH_BIG_1024_8].threads * kShapes[SH_BIG_1024_8].kp)
-                   ? SH_BIG_1024_8
+        return (prec != WK_FP64 && np <= (int64_t)kShapes[SH_BIG_512_8].threads * kShapes[SH_BIG_512_8].kp)
+                   ? SH_BIG_512_8
                    : SH_BIG_STREAM;
-    static const int order[] = {SH_256_4, SH_512_4, SH_512_16, SH_1024_8};
+    static const int order[] = {SH_256_4, SH_512_4, SH_512_8, SH_512_16, SH_1024_8};
     for (int sh : order) {
         const ShapeInfo& S = kShapes[sh];
         if (S.threads < threads) continue;
+        if (group > 1 && S.kp > 8) continue;
         if (np > (int64_t)S.threads * S.kp) continue;
         if (shape_lds_bytes(sh, n_nodes, prec) > kMaxLds) continue;
         return sh;
@@ -76,9 +77,15 @@ int march_occupancy(int prec, int geom, int warm, int shape, int max_nodes)
     return e == hipSuccess ? occ : 0;
 }
 
+size_t cycle_lds_bytes(int shape, int n_nodes, int prec)
+{
+    const size_t lds = shape_lds_bytes(shape, n_nodes, prec);
+    return kShapes[shape].big ? lds : lds + (size_t)kCycleRing * lds_stride(n_nodes) * sizeof(double);
+}
+
 hipError_t launch_cycle(const CycleDesc& c, int prec, int shape, int grid, hipStream_t s)
 {
-    const size_t lds = shape_lds_bytes(shape, c.base.n_r + 1, prec);
+    const size_t lds = cycle_lds_bytes(shape, c.base.n_r + 1, prec);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     const int warm = c.base.warm;
     if (prec == WK_FP64)
@@ -88,9 +95,11 @@ hipError_t launch_cycle(const CycleDesc& c, int prec, int shape, int grid, hipSt
                                  : launch_cycle_f32_slab(c, warm, shape, grid, lds, s, nullptr);
 }
 
+bool lds_fits(size_t bytes) { return bytes <= kMaxLds; }
+
 int cycle_occupancy(int prec, int geom, int warm, int shape, int n_nodes)
 {
-    const size_t lds = shape_lds_bytes(shape, n_nodes, prec);
+    const size_t lds = cycle_lds_bytes(shape, n_nodes, prec);
     if (lds > kMaxLds) return 0;
     CycleDesc c{};
     int occ = 0;

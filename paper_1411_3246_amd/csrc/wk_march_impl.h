@@ -47,8 +47,8 @@ __device__ __forceinline__ dev::Group member_group(const MarchDesc& full, int ra
     return grp;
 }
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
-__global__ __launch_bounds__(T) void k_march(MarchLaunch L)
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS>
+__global__ __launch_bounds__(T, WPS) void k_march(MarchLaunch L)
 {
     extern __shared__ double smem[];
     __shared__ int s_ticket;
@@ -83,7 +83,7 @@ hipError_t go(const MarchLaunch& L, int grid, size_t lds, hipStream_t s, int* oc
     if constexpr (S.big && S.resident && sizeof(R) == 8) {
         return hipErrorInvalidValue;
     } else {
-        auto kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big>;
+        auto kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd>;
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, S.threads, lds);
@@ -97,11 +97,12 @@ hipError_t go_shape(const MarchLaunch& L, int shape, int grid, size_t lds, hipSt
 {
     switch (shape) {
     case SH_256_4: return go<R, GEOM, WARM, SH_256_4>(L, grid, lds, s, occ);
+    case SH_512_8: return go<R, GEOM, WARM, SH_512_8>(L, grid, lds, s, occ);
     case SH_512_4: return go<R, GEOM, WARM, SH_512_4>(L, grid, lds, s, occ);
     case SH_512_16: return go<R, GEOM, WARM, SH_512_16>(L, grid, lds, s, occ);
     case SH_1024_8: return go<R, GEOM, WARM, SH_1024_8>(L, grid, lds, s, occ);
     case SH_1024_STREAM: return go<R, GEOM, WARM, SH_1024_STREAM>(L, grid, lds, s, occ);
-    case SH_BIG_1024_8: return go<R, GEOM, WARM, SH_BIG_1024_8>(L, grid, lds, s, occ);
+    case SH_BIG_512_8: return go<R, GEOM, WARM, SH_BIG_512_8>(L, grid, lds, s, occ);
     case SH_BIG_STREAM: return go<R, GEOM, WARM, SH_BIG_STREAM>(L, grid, lds, s, occ);
     default: return hipErrorInvalidValue;
     }

@@ -55,6 +55,14 @@ __device__ __forceinline__ void st_dev(V* p, V v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for this thread's global stores to be acknowledged.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 // Bounded waits: a wait gives up after kWaitTicks of the constant-rate
 // device clock (wall_clock64, 100 MHz) and raises the abort counter, so a
@@ -82,10 +90,11 @@ __device__ __forceinline__ void wait_at_least(const unsigned* p, unsigned need, 
 struct Group {
     int G = 1;                           // workgroups in the group
     int g = 0;                           // this workgroup's rank
-    double* xbuf = nullptr;              // [G][kXRows][stride] partial rows
+    double* xbuf = nullptr;              // [2][G][kXRows][stride] partial rows (two slots)
     unsigned* ctr = nullptr;             // arrival counter
     unsigned long long* abort = nullptr;
-    unsigned epoch = 0;                  // barriers passed
+    unsigned epoch = 0;                  // exchanges done
+    unsigned bars = 0;                   // counter barriers passed
 };
 
 // All threads: every thread's device-coherent stores are complete; arrive at
@@ -94,10 +103,10 @@ __device__ __forceinline__ void group_barrier(Group& grp)
 {
     wait_vm();
     __syncthreads();
-    ++grp.epoch;
+    ++grp.bars;
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(grp.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wait_at_least(grp.ctr, grp.epoch * (unsigned)grp.G, grp.abort);
+        wait_at_least(grp.ctr, grp.bars * (unsigned)grp.G, grp.abort);
     }
     __syncthreads();
 }
@@ -133,13 +142,19 @@ __device__ __forceinline__ double* scan_scratch()
     return s;
 }
 
-// Store wait of the large-grid variant: its node rows partly live in global
-// memory, so a barrier must also wait for this thread's stores.
+// Barrier of the march.  Its node rows are in LDS, so the barrier orders LDS
+// accesses only and does not wait for outstanding global stores (fields,
+// exchange rows).  The large-grid variant keeps node rows in global memory,
+// so there a barrier also waits for this thread's stores.
 template <bool GLOBAL_ROWS>
 __device__ __forceinline__ void block_sync()
 {
-    if (GLOBAL_ROWS) wait_vm();
-    __syncthreads();
+    if (GLOBAL_ROWS) {
+        wait_vm();
+        __syncthreads();
+    } else {
+        lds_barrier();
+    }
 }
 
 // Double value of lane `src` of the wavefront (two 32-bit permutes).
@@ -562,33 +577,114 @@ struct Marcher {
     }
 
     // ---- exchange between the workgroups of a group -------------------------
-    // Sum the deposit rows [r0, r0 + nr) over the G workgroups, in rank order,
-    // into every workgroup's LDS rows.  Every thread calls it (it contains the
-    // barriers); the caller synchronizes afterwards.
-    __device__ __forceinline__ void exchange(int r0, int nr)
+    // Sum the NR LDS rows ROWS (deposit rows, always in LDS) over the G
+    // workgroups, in rank order, into every workgroup's LDS rows.  Every
+    // thread calls it; the caller synchronizes afterwards.
+    //
+    // Exchange e (e = 1, 2, ... counted by every workgroup alike) writes the
+    // partial rows into buffer slot e % 2 with the two lowest mantissa bits of
+    // every value replaced by e % 4.  A reader loads the G partials of its
+    // items until every tag matches, so that no separate barrier or store
+    // acknowledgement is needed: a value carries its own epoch.  A workgroup
+    // can only write exchange e + 2 into a slot after it has read every
+    // partial of exchange e + 1, which each workgroup writes only after it has
+    // read exchange e, so a slot is never overwritten while it is read.  The
+    // slots start zeroed (tag 0) for every launch.  Clearing the two bits
+    // changes a partial by at most 2^-51 of itself, identically for every
+    // workgroup, so the group still sums identical values.
+    // ROWS: the LDS row numbers, 4 bits each (row q in bits 4q..4q+3), so that
+    // a row number is register arithmetic rather than a table lookup.
+    template <int NR, unsigned ROWS>
+    __device__ __forceinline__ static int xrow(int q)
     {
-        if (grp.G <= 1) return;
-        __syncthreads();                       // this workgroup's deposits are complete
+        return (int)((ROWS >> (4 * q)) & 15u);
+    }
+
+    template <int NR, unsigned ROWS>
+    __device__ __forceinline__ void exchange()
+    {
+        // the 16-particle shape marches single workgroups only
+        if (K > 8 || grp.G <= 1) return;
+        const unsigned e = ++grp.epoch;
         const int64_t part = (int64_t)kXRows * st;
-        double* mine = grp.xbuf + (int64_t)grp.g * part;
-        const int items = nr * N1;
+        double* slot = grp.xbuf + (int64_t)(e & 1u) * grp.G * part;
+        double* mine = slot + (int64_t)grp.g * part;
+        lds_barrier();                         // this workgroup's deposits are complete
+        const int items = NR * N1;
         for (int it = tid; it < items; it += T) {
-            const int r = r0 + it / N1, j = it % N1;
-            st_dev(mine + (int64_t)r * st + j, row(r)[j]);
+            const int q = it / N1, j = it - q * N1;
+            st_dev(mine + (int64_t)q * st + j, with_tag(sm[xrow<NR, ROWS>(q) * st + j], e));
         }
-        group_barrier(grp);
+        lds_barrier();                         // every row read before the sums overwrite it
+        if (grp.G <= 4) sum_partials<4, 4, NR, ROWS>(slot, part, e);
+        else if (grp.G <= 8) sum_partials<8, 2, NR, ROWS>(slot, part, e);
+        else sum_partials<kMaxGroup, 1, NR, ROWS>(slot, part, e);
+    }
+
+    __device__ __forceinline__ static double with_tag(double v, unsigned e)
+    {
+        return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(v) & ~3ull) | (e & 3u)));
+    }
+    __device__ __forceinline__ static unsigned tag_of(double v)
+    {
+        return (unsigned)((unsigned long long)__double_as_longlong(v) & 3ull);
+    }
+    __device__ __forceinline__ static double untagged(double v)
+    {
+        return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & ~3ull));
+    }
+
+    // The sums of exchange(): each thread takes items (row, node) tid + m T
+    // in batches of B, loads the partials of a batch (MAXG >= G per item)
+    // until all carry this exchange's tag, and adds them in rank order.
+    template <int MAXG, int B, int NR, unsigned ROWS>
+    __device__ __forceinline__ void sum_partials(const double* slot, int64_t part, unsigned e)
+    {
         const int G = grp.G;
-        for (int it = tid; it < items; it += T) {
-            const int r = r0 + it / N1, j = it % N1;
-            const double* src = grp.xbuf + (int64_t)r * st + j;
-            double v[kMaxGroup];
+        const int items = NR * N1;
+        const unsigned want = e & 3u;
+        for (int base = tid; base < items; base += B * T) {
+            double v[B][MAXG];
+            unsigned long long t0 = 0;
+            unsigned tries = 0;
+            for (;;) {
+                bool ok = true;
 #pragma unroll
-            for (int q = 0; q < kMaxGroup; ++q) v[q] = q < G ? ld_dev(src + q * part) : 0.0;
-            double s = v[0];
+                for (int c = 0; c < B; ++c) {
+                    const int it = base + c * T;
+                    const int q = it / N1, j = it - q * N1;
+                    const double* src = slot + (int64_t)q * st + j;
 #pragma unroll
-            for (int q = 1; q < kMaxGroup; ++q)
-                if (q < G) s += v[q];
-            row(r)[j] = s;
+                    for (int h = 0; h < MAXG; ++h) {
+                        const bool use = it < items && h < G;
+                        v[c][h] = use ? ld_dev(src + h * part) : 0.0;
+                        ok = ok && (!use || tag_of(v[c][h]) == want);
+                    }
+                }
+                if (ok) break;
+                // the abort flag and the clock are looked at every 64 tries
+                if ((++tries & 63u) == 0) {
+                    if (t0 == 0) {
+                        t0 = wall_clock64();
+                    } else if (wall_clock64() - t0 > kWaitTicks) {
+                        st_dev(grp.abort, 1ull);
+                        break;
+                    }
+                    if (ld_dev(grp.abort)) break;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                const int it = base + c * T;
+                if (it < items) {
+                    const int q = it / N1, j = it - q * N1;
+                    double s = untagged(v[c][0]);
+#pragma unroll
+                    for (int h = 1; h < MAXG; ++h)
+                        if (h < G) s += untagged(v[c][h]);
+                    sm[xrow<NR, ROWS>(q) * st + j] = s;
+                }
+            }
         }
     }
 
@@ -692,6 +788,41 @@ struct Marcher {
         }
     }
 
+    // All threads, two passes with a barrier between: this workgroup's deposits
+    // divided by the node volumes (rank 0 adds the beam current row when given;
+    // psi' of this stage's psi), then the right-hand side of the B_theta
+    // equation without its E_z term,
+    //   Q_j = d_r J_z - M2 psi' - a M3 + r^-a d_r(r^a M5)   (rows 1..N-1),
+    //   Q_N = (J_z,N + J_z,N-1) / 2                          (Eq. (6) at the wall),
+    // written over row M2.  Q is linear in the deposits, so the sums over a
+    // group of J_r, M1, M4 and Q are all the B_theta solve needs.
+    __device__ __forceinline__ void fold_moments(const double* jb_row)
+    {
+        finalize_moments(grp.g == 0 ? jb_row : nullptr);
+        sync();
+        const double a = GEOM == WK_CYL ? 1.0 : 0.0;
+        const double ih = rcp64(h);
+        const double* jz = row(ROW_JZ);
+        const double* m3 = row(ROW_M3);
+        const double* m5 = row(ROW_M5);
+        const double* dpsi = row(ROW_DPSI2);
+        double* q = row(ROW_M2);
+        for (int j = tid + 1; j <= N; j += T) {
+            double v;
+            if (j < N) {
+                const double irj = GEOM == WK_CYL ? rcp64((double)j * h) : 1.0;
+                const double rp = GEOM == WK_CYL ? (double)(j + 1) * h : 1.0;
+                const double rm = GEOM == WK_CYL ? (double)(j - 1) * h : 1.0;
+                const double m5flux = GEOM == WK_CYL ? (rp * m5[j + 1] - rm * m5[j - 1]) * (0.5 * ih) * irj
+                                                     : (m5[j + 1] - m5[j - 1]) * (0.5 * ih);
+                v = (jz[j + 1] - jz[j - 1]) * (0.5 * ih) - q[j] * dpsi[j] - a * m3[j] + m5flux;
+            } else {
+                v = 0.5 * (jz[N] + jz[N - 1]);
+            }
+            q[j] = v;
+        }
+    }
+
     // All threads: E_z = -int_r^{r_max} J_r dr' (Eq. (7), trapezoid rule), a
     // block-wide scan.
     __device__ __forceinline__ void solve_ez(double* ez)
@@ -714,6 +845,9 @@ struct Marcher {
     // All threads: B_theta from the Helmholtz form of Eq. (6) (rows 1..N-1) and
     // Eq. (6) at the wall (row N), by parallel cyclic reduction; then zero the
     // deposit rows for the next stage.  Needs a barrier before (E_z ready).
+    // FOLDED: the right-hand side without its M4 E_z term is in row M2
+    // (fold_moments); otherwise it is formed here from the moment rows.
+    template <bool FOLDED = false>
     __device__ __forceinline__ void solve_b(const double* dpsi, const double* ez, double* bt)
     {
         const double a = GEOM == WK_CYL ? 1.0 : 0.0;
@@ -738,9 +872,13 @@ struct Marcher {
                 A[i] = ih2 - a * (0.5 * ih) * irj;
                 B[i] = -2.0 * ih2 - a * irj * irj - m1[j];
                 C[i] = ih2 + a * (0.5 * ih) * irj;
-                const double m5flux = (rp * m5[j + 1] - rm * m5[j - 1]) * (0.5 * ih) * irj;
-                D[i] = (jz[j + 1] - jz[j - 1]) * (0.5 * ih) - m2[j] * dpsi[j] - (GEOM == WK_CYL ? m3[j] : 0.0)
-                       + m4[j] * ez[j] + (GEOM == WK_CYL ? m5flux : (m5[j + 1] - m5[j - 1]) * (0.5 * ih));
+                if (FOLDED) {
+                    D[i] = m2[j] + m4[j] * ez[j];
+                } else {
+                    const double m5flux = (rp * m5[j + 1] - rm * m5[j - 1]) * (0.5 * ih) * irj;
+                    D[i] = (jz[j + 1] - jz[j - 1]) * (0.5 * ih) - m2[j] * dpsi[j] - (GEOM == WK_CYL ? m3[j] : 0.0)
+                           + m4[j] * ez[j] + (GEOM == WK_CYL ? m5flux : (m5[j + 1] - m5[j - 1]) * (0.5 * ih));
+                }
             } else {
                 const double irh = GEOM == WK_CYL ? rcp64(((double)N - 0.5) * h) : 1.0;
                 const double rNm = GEOM == WK_CYL ? (double)(N - 1) * h : 1.0;
@@ -748,7 +886,7 @@ struct Marcher {
                 A[i] = -rNm * ih * irh;
                 B[i] = rN * ih * irh;
                 C[i] = 0.0;
-                D[i] = 0.5 * (jz[N] + jz[N - 1]);
+                D[i] = FOLDED ? m2[N] : 0.5 * (jz[N] + jz[N - 1]);
             }
         }
         sync();
@@ -860,6 +998,9 @@ struct Marcher {
     // psi, psi', E_z and the current/moment rows ready (B not yet solved),
     // after_b(k, stage, B) with B_theta solved.  No-ops by default.
     struct NoRecord {
+        // true: the moment rows J_z, M1..M5 are kept (for before_b) instead of
+        // being folded into the right-hand side of the B_theta equation
+        static constexpr bool kKeepMoments = false;
         __device__ __forceinline__ void before_b(Marcher&, int, int) {}
         __device__ __forceinline__ void after_b(Marcher&, int, int, const double*) {}
         // extra raw J_z deposits (before the exchange) at slice k
@@ -931,6 +1072,30 @@ struct Marcher {
         return derivative(p, psi1, dpsi1, b1);
     }
 
+    static constexpr unsigned kRowS = ROW_S;
+    static constexpr unsigned kRowsAll = ROW_JR | ROW_JZ << 4 | ROW_M1 << 8 | ROW_M2 << 12 | ROW_M3 << 16 |
+                                         ROW_M4 << 20 | ROW_M5 << 24;
+    static constexpr unsigned kRowsFold = ROW_JR | ROW_M1 << 4 | ROW_M2 << 8 | ROW_M4 << 12;
+
+    // The deposits of a stage -> the node rows the field solves use (all
+    // threads; ends with a barrier).  KEEP: every moment row is kept (a single
+    // workgroup); otherwise the moments are folded into J_r, M1, M4 and the
+    // right-hand side Q, and those four rows are summed over the group.
+    template <bool KEEP>
+    __device__ __forceinline__ void moments_to_rows(const double* jb_row)
+    {
+        if (KEEP) {
+            exchange<7, kRowsAll>();
+            sync();
+            finalize_moments(jb_row);
+        } else {
+            sync();
+            fold_moments(jb_row);
+            exchange<4, kRowsFold>();
+        }
+        sync();
+    }
+
     template <class Hooks>
     __device__ __forceinline__ void run(Hooks& hooks)
     {
@@ -974,7 +1139,7 @@ struct Marcher {
             for_parts<false>([&](int, Part<R>& p) { dep_S(a, p); });
             a.flush(row(ROW_S), st);
         }
-        exchange(ROW_S, 1);
+        exchange<1, kRowS>();
         for (int k = 0; k < d.n_xi; ++k) {
             hooks.before_slice(*this, k);
             const double* jb0 = hooks.jb_row(*this, k);
@@ -989,14 +1154,11 @@ struct Marcher {
                 flush_moments(a);
             }
             hooks.deposit_beam(*this, k);
-            exchange(ROW_JR, ROW_M5 - ROW_JR + 1);
-            sync();
-            finalize_moments(jb0);
-            sync();
+            moments_to_rows<Hooks::kKeepMoments>(jb0);
             solve_ez(ez);
             sync();
             hooks.before_b(*this, k, 0);
-            solve_b(dpsi2, ez, b1);
+            solve_b<!Hooks::kKeepMoments>(dpsi2, ez, b1);
             hooks.after_b(*this, k, 0, b1);
             // keep the stage-1 psi, psi' for the derivative
             sync();
@@ -1017,7 +1179,7 @@ struct Marcher {
                 });
                 a.flush(row(ROW_S), st);
             }
-            exchange(ROW_S, 1);
+            exchange<1, kRowS>();
             sync();
             solve_psi(psi2);
             sync();
@@ -1030,14 +1192,11 @@ struct Marcher {
                 flush_moments(a);
             }
             hooks.deposit_beam(*this, k + 1);
-            exchange(ROW_JR, ROW_M5 - ROW_JR + 1);
-            sync();
-            finalize_moments(hooks.jb_row(*this, k + 1));
-            sync();
+            moments_to_rows<Hooks::kKeepMoments>(hooks.jb_row(*this, k + 1));
             solve_ez(ez);
             sync();
             hooks.before_b(*this, k, 1);
-            solve_b(dpsi2, ez, b2);
+            solve_b<!Hooks::kKeepMoments>(dpsi2, ez, b2);
             hooks.after_b(*this, k, 1, b2);
             sync();
             // ---- corrector Y_{k+1} = Y_k + dxi/2 (f_k + f*), deposit S(Y_{k+1}) ----
@@ -1058,7 +1217,7 @@ struct Marcher {
                 });
                 a.flush(row(ROW_S), st);
             }
-            exchange(ROW_S, 1);
+            exchange<1, kRowS>();
         }
         if (RES && keep_state) {
             const int64_t i0 = (int64_t)blk * kr;
