@@ -18,7 +18,8 @@
  * Conventions for every call:
  *   - All buffers are caller-owned.  Pointers named d_* are device pointers
  *     (HIP device memory on the current device); h_* are host pointers.
- *     The library never allocates or frees device memory.
+ *     The library never allocates or frees device memory; its one static
+ *     device array (see wk_plasma_response_noalloc) comes with its code.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Work is enqueued asynchronously; argument errors are reported
  *     synchronously by the return value, device-side numeric events through
@@ -211,6 +212,28 @@ wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double*
 wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma,
                              const double* d_jb, void* d_fields, void* d_workspace,
                              uint64_t* d_counters, void* stream);
+
+/* Bytes of the library's static device scratch array (one per device). */
+#define WK_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* wk_plasma_response for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same march, with the exchange rows between workgroups,
+ * the group counter and the large-grid node rows in a static array of
+ * WK_NOALLOC_SCRATCH_BYTES bytes that every device the library runs on holds
+ * until the process ends, instead of a caller workspace.  It calls no
+ * allocator; the caller passes the inputs and outputs as for
+ * wk_plasma_response.  The call runs on the current device, and `stream`
+ * must belong to it.  The array holds the march region of every plan that
+ * wk_plan_create accepts (n_r <= 2048, up to 16 workgroups: about 7.1 MB);
+ * a response that needed more would return WK_ERR_UNSUPPORTED before
+ * anything is launched.  Every call on one device shares that
+ * device's array, which keeps the last call's contents (each call clears
+ * what must start at zero): calls that overlap on one device race, so
+ * serialise them (one stream, or events between streams). */
+wk_status wk_plasma_response_noalloc(const wk_plan* plan, const wk_plasma_bufs* plasma,
+                                     const double* d_jb, void* d_fields,
+                                     uint64_t* d_counters, void* stream);
 
 /* Launch shape: smallest workgroup size of the march kernel (256, 512 or
  * 1024; the launch may use a larger one to keep the particles in

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,13 +101,19 @@ int64_t member_np(const wk_plan* pl, int G) { return (int64_t)((pl->N + G - 1) /
 
 // March region at the start of a plan workspace: the large-grid node rows of
 // up to kMaxGroup workgroups, the group's partial rows and its counter.
-size_t march_grow_bytes(const wk_plan* pl) { return pl->big ? wk::kMaxGroup * a256(wk::big_rows_bytes(pl->N1)) : 0; }
 // exchange rows of a group: two slots of G partials of kXRows node rows
 size_t march_xbuf_bytes(int N1, int G)
 {
     return a256((size_t)2 * G * wk::kXRows * wk::lds_stride(N1) * sizeof(double));
 }
-size_t march_region_bytes(const wk_plan* pl) { return march_grow_bytes(pl) + march_xbuf_bytes(pl->N1, wk::kMaxGroup) + 256; }
+// Layout of a march region for `G` workgroups: the large-grid node rows, the
+// exchange rows, then the group counter.
+size_t march_grow_bytes(const wk_plan* pl, int G) { return pl->big ? G * a256(wk::big_rows_bytes(pl->N1)) : 0; }
+size_t march_region_bytes(const wk_plan* pl, int G)
+{
+    return march_grow_bytes(pl, G) + march_xbuf_bytes(pl->N1, G) + 256;
+}
+size_t march_region_bytes(const wk_plan* pl) { return march_region_bytes(pl, wk::kMaxGroup); }
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7) == 0; }
 
@@ -165,6 +172,57 @@ wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double
     d.xbuf = nullptr;
     d.gctr = nullptr;
     return d;
+}
+
+// One response from a march region at `ws` laid out for `layout_group`
+// workgroups (at least the group that marches it).
+wk_status response_in(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb, void* d_fields,
+                      char* ws, int layout_group, uint64_t* d_counters, hipStream_t s)
+{
+    const int G = single_group(plan);
+    const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec, G);
+    wk::MarchLaunch L{};
+    L.one = make_desc(plan, plasma, d_jb, d_fields, d_counters);
+    L.one.group = G;
+    L.one.xbuf = (double*)(ws + march_grow_bytes(plan, layout_group));
+    L.one.gctr = (unsigned*)(ws + march_grow_bytes(plan, layout_group) + march_xbuf_bytes(plan->N1, layout_group));
+    L.grow = plan->big ? (double*)ws : nullptr;
+    L.grow_stride = wk::lds_stride(plan->N1);
+    // the exchange slots start zeroed (tag 0) for every launch
+    hipError_t e = G > 1 ? wk::launch_zero_u32((unsigned*)L.one.xbuf, (int64_t)march_xbuf_bytes(plan->N1, G) / 4, s)
+                         : hipSuccess;
+    if (e == hipSuccess) e = wk::launch_zero_u32(L.one.gctr, 1, s);
+    if (e == hipSuccess)
+        e = wk::launch_march(L, plan->p.prec, plan->p.geom, L.one.warm, shape, G, plan->N1, s);
+    return hip_status(e, "plasma response");
+}
+
+// Scratch of wk_plasma_response_noalloc: the march region of one response,
+// resident on every device the library runs on.  Host code reaches it only
+// through the per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[WK_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+wk_status scratch_address(char** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(WK_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "scratch address");
+        if (!ptr) return fail(WK_ERR_HIP, "scratch address is NULL");
+        g_scratch[dev] = (char*)ptr;
+    }
+    *out = g_scratch[dev];
+    return WK_OK;
 }
 
 }  // namespace
@@ -354,24 +412,25 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
     wk_status st = check_plasma(plan, plasma);
     if (st != WK_OK) return st;
+    return response_in(plan, plasma, d_jb, d_fields, (char*)d_workspace, wk::kMaxGroup, d_counters,
+                       (hipStream_t)stream);
+}
+
+wk_status wk_plasma_response_noalloc(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb,
+                                     void* d_fields, uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_jb || !d_fields || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
     const int G = single_group(plan);
-    const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec, G);
-    char* ws = (char*)d_workspace;
-    wk::MarchLaunch L{};
-    L.one = make_desc(plan, plasma, d_jb, d_fields, d_counters);
-    L.one.group = G;
-    L.one.xbuf = (double*)(ws + march_grow_bytes(plan));
-    L.one.gctr = (unsigned*)(ws + march_grow_bytes(plan) + march_xbuf_bytes(plan->N1, wk::kMaxGroup));
-    L.grow = plan->big ? (double*)ws : nullptr;
-    L.grow_stride = wk::lds_stride(plan->N1);
-    hipStream_t s = (hipStream_t)stream;
-    // the exchange slots start zeroed (tag 0) for every launch
-    hipError_t e = G > 1 ? wk::launch_zero_u32((unsigned*)L.one.xbuf, (int64_t)march_xbuf_bytes(plan->N1, G) / 4, s)
-                         : hipSuccess;
-    if (e == hipSuccess) e = wk::launch_zero_u32(L.one.gctr, 1, s);
-    if (e == hipSuccess)
-        e = wk::launch_march(L, plan->p.prec, plan->p.geom, L.one.warm, shape, G, plan->N1, s);
-    return hip_status(e, "plasma response");
+    const size_t need = march_region_bytes(plan, G);
+    if (need > WK_NOALLOC_SCRATCH_BYTES)
+        return fail(WK_ERR_UNSUPPORTED, "response needs %zu bytes of scratch, the static array holds %zu", need,
+                    (size_t)WK_NOALLOC_SCRATCH_BYTES);
+    char* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != WK_OK) return st;
+    return response_in(plan, plasma, d_jb, d_fields, ws, G, d_counters, (hipStream_t)stream);
 }
 
 size_t wk_batch_desc_bytes(int32_t n)

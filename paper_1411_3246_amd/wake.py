@@ -68,6 +68,7 @@ EXPORTS = [
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle", "wk_plan_set_group", "wk_plan_group", "wk_cycle_group",
+    "wk_plasma_response_noalloc",
     "wk_gradient_workspace_size", "wk_gradient_forward", "wk_gradient_backward",
 ]
 
@@ -111,6 +112,7 @@ def lib():
     L.wk_beam_current_analytic.argtypes = [vp, vp, vp]
     L.wk_beam_current.argtypes = [vp, C.POINTER(WkBeamBufs), vp, vp, vp, vp]
     L.wk_plasma_response.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp, vp]
+    L.wk_plasma_response_noalloc.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp]
     L.wk_batch_desc_bytes.argtypes = [i32]
     L.wk_batch_desc_bytes.restype = C.c_size_t
     L.wk_batch_workspace_size.argtypes = [i32, C.POINTER(vp)]
@@ -293,6 +295,13 @@ class Plan:
                                         _ptr(workspace), _ptr(counters), _stream(stream)),
                "wk_plasma_response")
 
+    def plasma_response_noalloc(self, plasma: Dict, jb, fields, counters, stream=None):
+        """wk_plasma_response with the library's static scratch in place of a workspace."""
+        b = self.plasma_bufs(plasma)
+        _check(lib().wk_plasma_response_noalloc(self.handle, C.byref(b), _ptr(jb), _ptr(fields),
+                                                _ptr(counters), _stream(stream)),
+               "wk_plasma_response_noalloc")
+
     def beam_push(self, beam: Dict, fields, n_steps: int, dt: float, counters, stream=None):
         b = self.beam_bufs(beam)
         _check(lib().wk_beam_push(self.handle, C.byref(b), _ptr(fields), n_steps, dt,
@@ -422,6 +431,11 @@ class Simulation:
         """Load the plasma ahead of the beam and march it through the window."""
         self.plan.init_plasma(self.plasma, self.plasma_draws)
         self.plan.plasma_response(self.plasma, self.jb, self.fields, self.workspace, self.counters)
+
+    def response_noalloc(self):
+        """response() through the allocation-free entry point."""
+        self.plan.init_plasma(self.plasma, self.plasma_draws)
+        self.plan.plasma_response_noalloc(self.plasma, self.jb, self.fields, self.counters)
 
     def push(self, n_steps: int = 1, dt: Optional[float] = None):
         self.plan.beam_push(self.beam, self.fields, n_steps, self.problem.dt if dt is None else dt,
