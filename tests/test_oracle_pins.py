@@ -334,6 +334,95 @@ def test_p7_uniform_ez_exact_kick(O):
     assert np.all(b["px"] == 0) and np.all(b["x"] == 0)
 
 
+def _beam_at(x, y, gam):
+    b = {k: np.zeros(len(x)) for k in ("x", "y", "px", "py", "pz", "xi", "w")}
+    b["x"][:] = x
+    b["y"][:] = y
+    b["xi"][:] = 5.0
+    b["pz"][:] = np.sqrt(gam ** 2 - 1)
+    return b
+
+
+def test_p7_pure_magnetic_rotation(O):
+    """Eqs. (8)-(11) with E = 0 and an azimuthal B_theta = b0 (W = -B_theta,
+    so E_r = W + B_theta = 0): the field does no work, so gamma is conserved
+    to rounding; one step of an electron moving along +z turns its momentum
+    outwards (q v x B with q = -1, z x theta = -r) by the gyration angle
+    b0 dt / gamma, to third order in that angle; and after time t the radial
+    displacement is b0 t^2 / (2 gamma) while the angle stays small."""
+    p = _beam_problem()
+    b0, gam = 0.3, 1000.0
+    fields = np.zeros((4, p.n_xi, p.n_r + 1))
+    fields[2] = b0
+    fields[3] = -b0
+    errs = []
+    for dt in (50.0, 25.0):
+        b = _beam_at([0.5], [0.0], gam)
+        O.beam_push(p, b, fields, 1, dt)
+        phi = b0 * dt / gam
+        ang = np.arctan2(b["px"][0], b["pz"][0])
+        assert b["px"][0] > 0 and b["py"][0] == 0.0
+        errs.append(abs(ang - phi))
+        assert errs[-1] <= phi ** 3, (ang, phi)
+    assert 6.0 < errs[0] / errs[1] < 10.0, errs       # third order in the angle
+    b = _beam_at([0.5, 0.3], [0.0, 0.4], gam)
+    g0 = np.sqrt(1 + b["pz"] ** 2)
+    O.beam_push(p, b, fields, 20, 5.0)
+    g = np.sqrt(1 + b["px"] ** 2 + b["py"] ** 2 + b["pz"] ** 2)
+    assert np.max(np.abs(g - g0) / g0) <= 1e-14
+    dr = np.hypot(b["x"], b["y"]) - 0.5
+    assert np.all(np.abs(dr / (b0 * 100.0 ** 2 / (2 * gam)) - 1.0) < 0.1), dr
+    # a particle in the x-z plane stays in it; the other keeps its azimuth
+    assert b["y"][0] == 0.0
+    assert abs(np.arctan2(b["y"][1], b["x"][1]) - np.arctan2(0.4, 0.3)) < 1e-12
+
+
+def test_p7_ion_channel_with_btheta(O):
+    """The ion-channel orbit with B_theta != 0 at fixed E_r - B_theta = r/2:
+    an ultra-relativistic electron feels q (E_r - v_z B_theta), so adding
+    B_theta = 0.35 r (and the same to E_r) changes its orbit only through
+    (1 - v_z) B_theta ~ B_theta / (2 gamma^2) and the splitting of the
+    step; the orbit stays x0 cos(t / sqrt(2 gamma)) and within 1e-4 of the
+    B_theta = 0 orbit.  A sign error or a dropped magnetic rotation would
+    change the betatron frequency by 30 % or more."""
+    p = _beam_problem()
+    r = np.arange(p.n_r + 1) * p.r_max / p.n_r
+    gam, T = 1000.0, 1000.0
+    w = 1 / np.sqrt(2 * gam)
+    out = []
+    for bs in (0.0, 0.35):
+        fields = np.zeros((4, p.n_xi, p.n_r + 1))
+        fields[3] = 0.5 * r[None, :]
+        fields[2] = bs * r[None, :]
+        b = _beam_at([0.5, 0.2], [0.0, 0.1], gam)
+        O.beam_push(p, b, fields, 1000, T / 1000)
+        assert abs(b["x"][0] - 0.5 * np.cos(w * T)) < 1e-2
+        assert abs(b["y"][1] - 0.1 * np.cos(w * T)) < 2e-3
+        out.append(np.array([b["x"][0], b["x"][1], b["y"][1]]))
+    assert np.max(np.abs(out[1] - out[0])) < 1e-4, out
+
+
+def test_ez_peak_prescribed_field(O):
+    """The E_z spike diagnostic on a prescribed field: on axis
+    E_z(0, xi) = (xi - 6.3)^2 - 2 behind xi_from, a deeper minimum (-5) ahead
+    of xi_from, deeper values off axis (-9) and in the psi plane (-100): the
+    result is the on-axis minimum over slices xi_k >= xi_from, i.e. -2 at
+    xi = 6.3 (a node), -1.99 when xi_from moves past it, and the minimum
+    of the whole axis when xi_from is before the window."""
+    p = inputs.Problem(geom="cyl", n_r=8, r_max=2.0, n_xi=100, xi_max=10.0, ppc=1, sigma_r=0.3,
+                       bunches=[inputs.Bunch(1.0, 1.0, 5.0)], prec="fp64")
+    xi = p.xi_min + np.arange(p.n_xi) * p.dxi
+    fields = np.zeros((4, p.n_xi, p.n_r + 1))
+    fields[1, :, 0] = (xi - 6.3) ** 2 - 2.0
+    fields[1, 10, 0] = -5.0
+    fields[1, :, 3] = -9.0
+    fields[0, :, 0] = -100.0
+    assert O.ez_peak(p, fields, 5.0) == pytest.approx(-2.0, abs=1e-12)
+    assert O.ez_peak(p, fields, 6.3 - 1e-9) == pytest.approx(-2.0, abs=1e-12)
+    assert O.ez_peak(p, fields, 6.35) == pytest.approx(-1.99, abs=1e-12)
+    assert O.ez_peak(p, fields, -1.0) == -5.0
+
+
 def test_beam_loader_and_current(O):
     """Beam macroparticles reproduce the charge of Eq. (12) and the deposit
     conserves it."""
