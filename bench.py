@@ -32,32 +32,85 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32
 # Algorithmic bytes per plasma particle-slice update in the mixed mode: the
 # method's particle state (r, p_r) in double read and written (32 B) and
 # (l_z, D0, w) in float read (12 B) once per slice.
 BYTES_PER_UPDATE = 44.0
-# Scaled FETCH_SIZE + WRITE_SIZE of the cycle kernel, recorded with rocprofv3
-# for a given kernel-source hash; reported only while the sources match.
-COUNTERS = os.path.join(ROOT, "profiles", "k_cycle_two-bunch-512x4096-ppc16-beam1e6.counters.json")
-KERNEL_SOURCES = ("wk_cycle.hip", "wk_marcher.h", "wk_beam_dev.h", "wk_internal.h")
+# Algorithmic floating-point operations per update (both Heun stages of the
+# per-particle work: radius and radial momentum, the S deposit, gamma and p_z
+# from psi, seven moment deposits, the derivative and the state update, plus
+# the per-slice grid solves spread over the particles; counted from the
+# equations, an FMA as two).
+FLOPS_PER_UPDATE = 190.0
+# HBM bytes per update of the cycle kernel and of the batched march, from
+# scaled FETCH_SIZE + WRITE_SIZE counter runs (rocprofv3 --pmc), recorded for
+# a hash of the kernel sources; reported only while the sources match.
+PROFILES = os.path.join(ROOT, "profiles")
+CYCLE_COUNTERS = os.path.join(PROFILES, "k_cycle_two-bunch-512x4096-ppc16-beam1e6.counters.json")
+SCAN_COUNTERS = os.path.join(PROFILES, "k_march_batch_scan-256.counters.json")
+KERNEL_SOURCES = ("wk_cycle_impl.h", "wk_march_impl.h", "wk_marcher.h", "wk_beam_dev.h", "wk_internal.h")
 
 
-def measured_traffic(steps: int):
-    """HBM bytes per launch from the committed counter run, or None when the
-    kernel sources changed since it was taken or the launch differs."""
+def source_hash() -> str:
     import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1411_3246_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path: str, updates: float):
+    """HBM bytes of a launch of `updates` particle-slice updates from the
+    committed counter record, or None when the kernel sources changed since
+    it was taken."""
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             rec = json.load(f)
-        h = hashlib.sha256()
-        for name in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, "paper_1411_3246_amd", "csrc", name), "rb") as f:
-                h.update(f.read())
+        if source_hash() != rec.get("source_hash"):
+            return None
     except OSError:
         return None
-    if h.hexdigest()[:16] != rec.get("source_hash") or rec.get("steps") != steps:
-        return None
-    return rec["traffic_bytes"]
+    return rec["bytes_per_update"] * updates
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Host threads for the multi-core oracle run: the cores this process may
+    use, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def roofline(updates: float, ms: float, traffic, kernel: str, launches: int) -> dict:
+    """Roofline entry of a launch: algorithmic HBM bytes against the HBM peak.
+    The method's algorithmic intensity (FLOPS_PER_UPDATE / BYTES_PER_UPDATE,
+    about 4.3 flop/B) is below the FP32 ridge point (157.3 / 8 = 19.7 flop/B),
+    so HBM is the roof; the FP32 fraction is given beside it."""
+    achieved = BYTES_PER_UPDATE * updates / (ms * 1e-3) / 1e9
+    flops = FLOPS_PER_UPDATE * updates / (ms * 1e-3) / 1e12
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "launches": launches,
+            "ms_per_launch": ms / launches, "bytes_per_update": BYTES_PER_UPDATE,
+            "traffic_unit": "bytes per launch",
+            "intensity_flop_per_byte": FLOPS_PER_UPDATE / BYTES_PER_UPDATE,
+            "fp32_tflops": flops, "fp32_frac": flops / FP32_PEAK_TFLOPS,
+            "limiter": "latency: the per-slice chain of barriers and exchanges between the workgroups "
+                       "of a response, not bandwidth or issue rate"}
 
 
 def parse():
@@ -76,6 +129,8 @@ def parse():
                     help="skip the batched 256-instance parameter scan")
     ap.add_argument("--scan-instances", type=int, default=256)
     ap.add_argument("--scan-reps", type=int, default=3, help="timed graph replays of the scan")
+    ap.add_argument("--scan-cpu-slices", type=int, default=96,
+                    help="slices of each scan instance in the multi-core oracle baseline")
     ap.add_argument("--workload", choices=["headline", "convergence", "te-scan", "table1-beam"],
                     default="headline",
                     help="convergence: the 2048-cell cylindrical (2048 x 16384) and slab (2048 x 8192) "
@@ -103,19 +158,21 @@ def cpu_baseline(p, fraction: float):
     O.march(sub, st, np.ascontiguousarray(jb[:n_xi]))
     dt = time.perf_counter() - t0
     upd = q.n_plasma * (n_xi - 1)
-    return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+    return {"value": upd / dt, "unit": "updates/s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
             "sample": f"one FP64 plasma response of the same workload, {n_xi} of {q.n_xi} slices, "
                       f"{q.n_plasma} particles per slice ({upd:.3g} updates, {dt:.1f} s, serial C)"}
 
 
 def scan_bench(args, log):
     """The batched parameter scan: every instance of the scan marched in one
-    persistent launch (shape picked by the autotuner, the whole pass replayed
-    from a HIP graph) against the same instances run one launch at a time.
+    persistent launch (each instance by a group of workgroups sized to its
+    cost, shape picked by the autotuner, the whole pass replayed from a HIP
+    graph), against the roofline and against the same instances run one
+    standalone response at a time (each with its own group).
 
-    The one-at-a-time time is measured on every instance with its xi window
-    cut to 128 slices and scaled by (n_xi - 1) / 127: a response costs the
-    same per slice, so this keeps the baseline to a few seconds."""
+    The standalone time is measured on every instance with its xi window cut
+    to 128 slices and scaled by (n_xi - 1) / 127 (a response costs the same
+    per slice); the scaling is checked on a few instances run whole."""
     import torch
     from paper_1411_3246_amd import autotune, inputs, wake
     probs = inputs.scan_instances(args.scan_instances)
@@ -137,27 +194,39 @@ def scan_bench(args, log):
     del scan
     torch.cuda.empty_cache()
 
+    def standalone(qs, idx):
+        sc = wake.Scan(qs)
+        for i in idx:                    # warm-up of every kernel variant
+            sc.run_one(i)
+        torch.cuda.synchronize()
+        out = []
+        for i in idx:
+            ev[0].record(stream)
+            sc.run_one(i)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            out.append(ev[0].elapsed_time(ev[1]))
+        del sc
+        torch.cuda.empty_cache()
+        return out
+
     cut = 128
-    short = wake.Scan([q.replace(n_xi=cut) for q in probs])
-    for i in range(len(probs)):            # warm-up of every kernel variant
-        short.run_one(i)
-    torch.cuda.synchronize()
-    seq_ms = 0.0
-    for i, q in enumerate(probs):
-        ev[0].record(stream)
-        short.run_one(i)
-        ev[1].record(stream)
-        ev[1].synchronize()
-        seq_ms += ev[0].elapsed_time(ev[1]) * (q.n_xi - 1) / (cut - 1)
-    del short
-    torch.cuda.empty_cache()
-    return {
+    short = standalone([q.replace(n_xi=cut) for q in probs], range(len(probs)))
+    est = [t * (q.n_xi - 1) / (cut - 1) for t, q in zip(short, probs)]
+    check_idx = list(range(0, len(probs), max(1, len(probs) // 4)))[:4]
+    whole = standalone([probs[i] for i in check_idx], range(len(check_idx)))
+    seq_ms = sum(est)
+    line = {
         "instances": len(probs),
         "updates": updates,
         "batched_ms": batched_ms,
         "batched_updates_per_s": updates / (batched_ms * 1e-3),
-        "sequential_ms_est": seq_ms,
+        "roofline": roofline(updates, batched_ms, measured_traffic(SCAN_COUNTERS, updates),
+                             "k_march (batched)", 1),
+        "standalone_ms_est": seq_ms,
         "batched_speedup": seq_ms / batched_ms,
+        "standalone_scaling_check": [{"instance": probs[i].name, "whole_ms": w, "scaled_ms": est[i]}
+                                     for i, w in zip(check_idx, whole)],
         "shape": {"threads": best[0], "wg_per_cu": best[1]},
         "tuner": table,
         "graph": True,
@@ -165,6 +234,45 @@ def scan_bench(args, log):
         "recipe": "u_th~U[0,0.05], sep~U[3,6], n_r in {128,256,512,1024}, n_xi~U{1024..4096}, "
                   "ppc in {8..32 even}, fixed analytic two-bunch beam, mixed precision",
     }
+    if not args.no_cpu:
+        line["cpu_baseline"] = scan_cpu_baseline(probs, args.scan_cpu_slices)
+    return line
+
+
+def scan_cpu_baseline(probs, n_slices: int):
+    """The FP64 oracle on every host thread this process may use: each
+    thread marches whole instances of the scan (their first `n_slices`
+    slices) one after another; the oracle is serial C, so the scan's
+    instances are the unit of parallel work."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    from paper_1411_3246_amd import inputs
+    O.lib()
+    jobs = []
+    for p in probs:
+        q = p.replace(prec="fp64", n_xi=min(n_slices, p.n_xi))
+        jobs.append(q)
+
+    def setup(q):
+        return q, O.load_plasma(q, inputs.plasma_draws(q)), np.ascontiguousarray(O.beam_current_analytic(q))
+
+    def one(job):
+        q, st, jb = job
+        O.march(q, st, jb)
+        return q.n_plasma * (q.n_xi - 1)
+
+    threads = host_threads()
+    with ThreadPoolExecutor(threads) as ex:
+        ready = list(ex.map(setup, jobs))
+        t0 = time.perf_counter()
+        upd = sum(ex.map(one, ready))
+        dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"every one of the {len(jobs)} scan instances in FP64, its first {n_slices} slices "
+                      f"({upd:.3g} updates, {dt:.1f} s on {threads} threads, one instance per thread at a "
+                      f"time; loading outside the timed marches)"}
 
 
 def grad_bench(args):
@@ -392,6 +500,7 @@ def main():
         return
     p = inputs.blowout_response().replace(n_steps=args.steps)
     sim = wake.Simulation(p, threads=args.threads)
+    group = sim.plan.cycle_group(args.steps) if args.mode == "pipelined" else sim.plan.group
     stream = torch.cuda.current_stream()
     upd_per_step = p.updates_per_response()
 
@@ -443,13 +552,12 @@ def main():
         kernel, launches = "k_cycle", 1
     else:
         kernel_ms = kt
-        kernel, launches = "k_march_one", args.steps
+        kernel, launches = "k_march", args.steps
     updates = upd_per_step * args.steps
     value = updates / elapsed
     counters = sim.counters_dict()
     gain = float(sim.out[0].item())
-    achieved = BYTES_PER_UPDATE * updates / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.steps) if args.mode == "pipelined" else None
+    traffic = measured_traffic(CYCLE_COUNTERS, updates) if args.mode == "pipelined" else None
     line = {
         "metric": "plasma particle-slice updates/s at 1 GPU",
         "value": value,
@@ -467,19 +575,15 @@ def main():
                    "ppc": p.ppc, "u_th": p.u_th, "n_beam": p.n_beam, "beam_steps_timed": args.steps,
                    "dt": p.dt, "mode": args.mode,
                    "precision": "FP32 bulk; FP64 solves, deposit accumulation and xi integration",
-                   "march_threads": sim.plan.threads},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel, "launches": launches,
-                     "ms_per_launch": kernel_ms / launches,
-                     "bytes_per_update": BYTES_PER_UPDATE,
-                     "traffic_unit": "bytes per launch"},
+                   "march_threads": sim.plan.threads, "group": group},
+        "roofline": roofline(updates, kernel_ms, traffic, kernel, launches),
         "diagnostics": {"witness_mean_gain_gamma": gain, "counters": counters},
     }
     if not args.no_scan:
         sc = scan_bench(args, lambda row: print(f"# tuner {row}", file=sys.stderr, flush=True))
         line["batched_scan"] = sc
         line["batched_speedup"] = sc["batched_speedup"]
+        line["batched_updates_per_s"] = sc["batched_updates_per_s"]
     if not args.no_grad:
         gr = grad_bench(args)
         line["gradient"] = gr

@@ -355,10 +355,12 @@ struct Marcher {
     static constexpr bool kBig = BIG;
     static constexpr int kT = T;
     // With few resident particles per thread, D0 and w live in registers
-    // (else in LDS slots) and the stage-1 derivative is kept in registers
-    // between the three passes that use it (else recomputed).
+    // (else in LDS slots); with at most four, the stage-1 derivative is also
+    // kept in registers between the three passes that use it (else
+    // recomputed: caching it for eight float particles costs more in spilled
+    // registers than the recomputation).
     static constexpr bool kRegConst = RES && (K <= 4 || (K <= 8 && sizeof(R) == 4));
-    static constexpr bool kCacheF = kRegConst;
+    static constexpr bool kCacheF = RES && K <= 4;
     MarchDesc d;
     double* sm;
     int st, N, N1, tid, lane, wid, blk;
@@ -648,6 +650,7 @@ struct Marcher {
             unsigned long long t0 = 0;
             unsigned tries = 0;
             for (;;) {
+                // every value of the batch, all loads in flight at once
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < B; ++c) {
@@ -662,15 +665,22 @@ struct Marcher {
                     }
                 }
                 if (ok) break;
-                // the abort flag and the clock are looked at every 64 tries
-                if ((++tries & 63u) == 0) {
-                    if (t0 == 0) {
-                        t0 = wall_clock64();
-                    } else if (wall_clock64() - t0 > kWaitTicks) {
-                        st_dev(grp.abort, 1ull);
-                        break;
+                if (++tries > 64) {
+                    // a long wait (a partner not yet started, as when a batch
+                    // hands out a group's tickets over time): about 1 us
+                    // between tries, so that waiting workgroups do not flood
+                    // memory with reads; the abort flag and the clock are
+                    // looked at every 64 tries
+                    __builtin_amdgcn_s_sleep(32);
+                    if ((tries & 63u) == 0) {
+                        if (t0 == 0) {
+                            t0 = wall_clock64();
+                        } else if (wall_clock64() - t0 > kWaitTicks) {
+                            st_dev(grp.abort, 1ull);
+                            break;
+                        }
+                        if (ld_dev(grp.abort)) break;
                     }
-                    if (ld_dev(grp.abort)) break;
                 }
             }
 #pragma unroll

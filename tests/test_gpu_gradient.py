@@ -1,8 +1,9 @@
 """Reverse-mode gradient of the witness gain on the GPU (recording FP64
 march, hand-written adjoint) against the FP64 oracle: the objective itself,
-and the gradient against the oracle's central finite differences (O9 of the
-method's test plan: fixed draws, step 1e-4 |theta_i|, Richardson-combined),
-within max(1e-4 |g_fd|, 3 x the finite-difference truncation estimate)."""
+and the gradient against the oracle's central finite differences (fixed
+draws, step 1e-4 |theta_i|, Richardson-combined; a component whose estimates
+at h and h/2 disagree is taken again at a smaller step), within 1e-4 of each
+component, the finite differences themselves resolving that bar."""
 import numpy as np
 import pytest
 
@@ -41,13 +42,36 @@ def _gpu(W, p, every=64):
     return g, grad, run
 
 
+def _fd(O, p, which):
+    """Richardson central differences of the oracle's objective at the
+    configured step (1e-4 of each parameter); a component whose estimates at
+    h and h/2 differ by more than 1e-5 of it (the objective is piecewise
+    smooth: a particle crossing a cell edge puts a kink in it, and a step
+    that straddles one is not a derivative) is taken again at 1e-5, then
+    1e-6.  Returns the derivative and the h vs h/2 gap it carries."""
+    fd, err = O.fd_gradient(p, which=which)
+    for rel_h in (1e-5, 1e-6):
+        redo = [i for i in which if err[i] > 1e-5 * abs(fd[i])]
+        if not redo:
+            break
+        g2, e2 = O.fd_gradient(p, rel_h=rel_h, which=redo)
+        for i in redo:
+            if e2[i] < err[i]:
+                fd[i], err[i] = g2[i], e2[i]
+    return fd, err
+
+
 def _compare(grad, fd, err, which=range(5)):
+    # the bar: 1e-4 of each component (with a floor of 1e-10 of the largest
+    # one for components that vanish); the reference must resolve it
+    scale = max(abs(fd[i]) for i in which)
     for i in which:
-        tol = max(1e-4 * abs(fd[i]), 3.0 * err[i], 1e-12)
+        tol = 1e-4 * abs(fd[i]) + 1e-10 * scale
         print(f"  {inputs.THETA_NAMES[i]:>14s} adjoint {grad[i]: .10e} fd {fd[i]: .10e} "
-              f"|diff| {abs(grad[i] - fd[i]):.2e} tol {tol:.2e}", flush=True)
+              f"|diff| {abs(grad[i] - fd[i]):.2e} tol {tol:.2e} h-vs-h/2 {err[i]:.2e}", flush=True)
     for i in which:
-        tol = max(1e-4 * abs(fd[i]), 3.0 * err[i], 1e-12)
+        tol = 1e-4 * abs(fd[i]) + 1e-10 * scale
+        assert err[i] <= tol, ("finite differences do not resolve the bar", inputs.THETA_NAMES[i], err[i])
         assert abs(grad[i] - fd[i]) <= tol, (inputs.THETA_NAMES[i], grad[i], fd[i])
 
 
@@ -55,7 +79,7 @@ def test_objective_matches_oracle(O, W):
     p = _case()
     print(f"case {p.name}", flush=True)
     g, _, run = _gpu(W, p)
-    assert g == pytest.approx(O.objective(p), rel=1e-9, abs=1e-12)
+    assert g == pytest.approx(O.objective(p), rel=1e-10, abs=1e-12)
     c = W.counters_dict(run.counters)
     assert c["nonfinite"] == 0 and c["wall"] == 0
 
@@ -68,7 +92,7 @@ def test_adjoint_matches_finite_differences(O, W, kw):
     print(f"case {kw}", flush=True)
     _, grad, _ = _gpu(W, p)
     which = (0, 1, 2, 3, 4) if p.u_th > 0 else (0, 1, 2, 3)
-    fd, err = O.fd_gradient(p, which=which)
+    fd, err = _fd(O, p, which)
     _compare(grad, fd, err, which)
     if p.u_th == 0:
         assert grad[4] == 0.0
@@ -103,6 +127,6 @@ def test_gradient_case_full_size_weak_driver(O, W):
     p = inputs.gradient_case(n_d=0.1).replace(u_th=0.005)
     print(f"case {p.name} n_d=0.1", flush=True)
     g, grad, run = _gpu(W, p, every=64)
-    assert g == pytest.approx(O.objective(p), rel=1e-9)
-    fd, err = O.fd_gradient(p, which=(0, 2, 3))
+    assert g == pytest.approx(O.objective(p), rel=1e-10)
+    fd, err = _fd(O, p, (0, 2, 3))
     _compare(grad, fd, err, (0, 2, 3))
