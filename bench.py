@@ -416,41 +416,103 @@ def te_scan_bench(args):
             "counters": wake.counters_dict(scan.counters), "rows": rows}
 
 
+def table1_trajectories(te: float) -> dict:
+    """Plasma electron trajectories behind the Table I driver (fixed beam,
+    256 x 2800, 16 ppc, FP64), every macroparticle recorded at every slice,
+    the width in xi over which the expelled electrons come back to the axis
+    (axis_crossings), and the E_r - B_theta field around the on-axis E_z
+    spike.  W = E_r - B_theta is
+    the radial force on a beam electron up to its sign (F_r = -W): W < 0 near
+    the axis at the spike means a defocusing region."""
+    import numpy as np
+    import torch
+    from paper_1411_3246_amd import diagnostics, inputs, wake
+    p = inputs.facet_table1(te, n_r=256, n_xi=2800, ppc=16, prec="fp64")
+    sim = wake.Simulation(p)
+    sim.beam_current()
+    stride = 1
+    tr = sim.response_traj(stride).cpu().numpy()
+    f = sim.fields.double().cpu().numpy()
+    torch.cuda.synchronize()
+    xi = p.xi_min + np.arange(p.n_xi) * p.dxi
+    h = p.r_max / p.n_r
+    xd = p.bunches[0].xi_c
+    k_from = int(np.searchsorted(xi, xd + 1.0))
+    ks = k_from + int(np.argmin(f[1, k_from:, 0]))
+    crossing = diagnostics.axis_crossings(tr, xi, h, xd)
+    w_axis = f[3, ks, 1:6]
+    out = {
+        "workload": p.name, "stride": stride, "recorded": int(tr.shape[1]),
+        "spike_ez": float(f[1, ks, 0]), "spike_xi": float(xi[ks]),
+        "axis_crossing": crossing,
+        "W_at_spike_r_h_to_5h": [float(v) for v in w_axis],
+        "W_map": {"xi": [float(xi[k]) for k in range(ks - 40, ks + 41, 10)],
+                  "r": [float(j * h) for j in (1, 2, 4, 8, 16, 32)],
+                  "W": [[float(f[3, k, j]) for j in (1, 2, 4, 8, 16, 32)] for k in range(ks - 40, ks + 41, 10)]},
+        "spike_in_defocusing_region": bool(np.all(w_axis < 0.0)),
+        "counters": sim.counters_dict(),
+    }
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def table1_beam_bench(args):
     """The Table I beam (1e6 macroparticles, zero emittance) evolved over
     1.14 m of plasma at 5e16 cm^-3 (1203 steps of 40 / omega_p) by the
-    pipelined cycle, in a cold and in a 5 eV plasma (256 x 2800 grid): the
-    witness mean gain and spread, the gain of the witness core (95th
-    percentile), the drive's mean energy change and the on-axis spike."""
+    pipelined cycle, in a cold and in a 5 eV plasma (256 x 2800 grid):
+    the witness energy spectrum (wk_gain_histogram, 0.5 GeV bins) with its
+    mean and its peak, the spread, the drive's mean energy change and the
+    on-axis spike; where the particles that leave the window are, by bunch;
+    and the plasma trajectories and E_r - B_theta map of the fixed-beam
+    response (table1_trajectories)."""
+    import numpy as np
     import torch
     from paper_1411_3246_amd import inputs, wake
     out = {}
     gev = 0.51099895e-3
+    n_bins, lo_gev, hi_gev = 80, -10.0, 30.0
     for te in (0.0, 5.0):
         p = inputs.facet_table1_beam(te)
         sim = wake.Simulation(p)
         sim.load_beam()
-        g0 = sim.beam["gamma_init"].clone()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record(torch.cuda.current_stream())
         sim.run_cycle(p.n_steps)
         ev[1].record(torch.cuda.current_stream())
         torch.cuda.synchronize()
-        b = sim.beam
-        dg = torch.sqrt(1 + b["px"] ** 2 + b["py"] ** 2 + b["pz"] ** 2) - g0
-        wit = b["tag"] == 1
         ms = ev[0].elapsed_time(ev[1])
+        hist = sim.gain_histogram(1, n_bins, lo_gev / gev, hi_gev / gev).cpu().numpy()
+        b = {k: sim.beam[k].cpu().numpy() for k in ("x", "y", "xi", "px", "py", "pz", "gamma_init", "tag")}
+        dg = np.sqrt(1 + b["px"] ** 2 + b["py"] ** 2 + b["pz"] ** 2) - b["gamma_init"]
+        wit = b["tag"] == 1
+        r = np.hypot(b["x"], b["y"])
+        centres = lo_gev + (np.arange(n_bins) + 0.5) * (hi_gev - lo_gev) / n_bins
+        peak = int(np.argmax(hist[1:-1]))
+        outside = {}
+        for name, sel in (("drive", ~wit), ("witness", wit)):
+            outside[name] = {"particles": int(sel.sum()),
+                             "beyond_r_max": int(np.sum(sel & (r > p.r_max))),
+                             "behind_window": int(np.sum(sel & (b["xi"] >= p.xi_max))),
+                             "ahead_of_window": int(np.sum(sel & (b["xi"] < p.xi_min)))}
+        c = sim.counters_dict()
         out[f"{te:g}eV"] = {
             "workload": p.name, "steps": p.n_steps, "ms": ms,
             "updates_per_s": p.updates_per_response() * p.n_steps / (ms * 1e-3),
-            "witness_gain_gamma": sim.witness_gain(), "witness_gain_GeV": sim.witness_gain() * gev,
-            "witness_gain_std_gamma": float(dg[wit].std()),
-            "witness_core_gain_GeV": float(torch.quantile(dg[wit], 0.95)) * gev,
+            "witness_mean_gain_GeV": sim.witness_gain() * gev,
+            "witness_gain_std_GeV": float(dg[wit].std()) * gev,
+            "witness_spectrum": {"bins_GeV": [lo_gev, hi_gev, n_bins], "underflow": int(hist[0]),
+                                 "overflow": int(hist[-1]), "counts": [int(v) for v in hist[1:-1]],
+                                 "peak_GeV": float(centres[peak])},
+            "witness_p95_gain_GeV": float(np.quantile(dg[wit], 0.95)) * gev,
             "drive_mean_dgamma": float(dg[~wit].mean()), "ez_spike_last": sim.ez_peak(6.04),
-            "counters": sim.counters_dict()}
+            "outside_window_at_end": outside,
+            "counters": c}
         print(f"# table1 beam {te:g} eV done", file=sys.stderr, flush=True)
         del sim
         torch.cuda.empty_cache()
+        out[f"{te:g}eV"]["trajectories"] = table1_trajectories(te)
+        print(f"# table1 trajectories {te:g} eV done", file=sys.stderr, flush=True)
     return out
 
 

@@ -213,6 +213,18 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma,
                              const double* d_jb, void* d_fields, void* d_workspace,
                              uint64_t* d_counters, void* stream);
 
+/* wk_plasma_response that also records plasma electron trajectories (the
+ * particle radius r = |(x, y)|, slab |x|, of every stride-th macroparticle,
+ * i = 0, stride, 2 stride, ... of the loaded order, at every slice k: the
+ * state the slice's fields are computed from), for the discussion of the
+ * trajectories behind the driver in Section III.  FP64 plans only
+ * (WK_ERR_UNSUPPORTED otherwise).  d_traj: double[n_xi][ceil(n_plasma /
+ * stride)], written entirely; the other arguments as for wk_plasma_response. */
+wk_status wk_plasma_response_traj(const wk_plan* plan, const wk_plasma_bufs* plasma,
+                                  const double* d_jb, void* d_fields, void* d_workspace,
+                                  int32_t stride, double* d_traj, uint64_t* d_counters,
+                                  void* stream);
+
 /* Bytes of the library's static device scratch array (one per device). */
 #define WK_NOALLOC_SCRATCH_BYTES (8u << 20)
 
@@ -318,6 +330,16 @@ wk_status wk_beam_push(const wk_plan* plan, const wk_beam_bufs* beam, const void
  * workspace). */
 wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which,
                        double* d_out, void* d_workspace, void* stream);
+/* Diagnostic: energy spectrum of the beam (Section III, the witness energy
+ * spectra): counts of the gain gamma - gamma_init of the particles with
+ * tag == which (all particles when which < 0) in n_bins (1..4096) equal bins
+ * of [lo, hi).  d_hist: uint64[n_bins + 2], written entirely: [0] below lo,
+ * [1..n_bins] the bins, [n_bins + 1] at or above hi.  Each particle's bin is
+ * decided in double with every operation rounded separately, so the counts
+ * are exact and independent of scheduling. */
+wk_status wk_gain_histogram(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which,
+                            int32_t n_bins, double lo, double hi, uint64_t* d_hist,
+                            void* stream);
 /* Diagnostic: most negative on-axis E_z over slices with xi_k >= xi_from, written
  * to d_out[0] as double. */
 wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,

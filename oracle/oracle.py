@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
+_up = C.POINTER(C.c_uint64)
 
 
 class OrProblem(C.Structure):
@@ -56,6 +57,10 @@ def lib():
         L.or_mean_gain.argtypes = [C.c_int64, _ip, C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.or_mean_gain.restype = C.c_double
         L.or_ez_peak.argtypes = [P, _dp, C.c_double]
+        L.or_march_traj.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _lp,
+                                    C.c_int32, _dp]
+        L.or_gain_histogram.argtypes = [C.c_int64, _ip, C.c_int32, _dp, _dp, _dp, _dp, C.c_int32,
+                                        C.c_double, C.c_double, _up]
         L.or_ez_peak.restype = C.c_double
         L.or_thomas.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp]
         for name in ("or_load_plasma", "or_beam_current_analytic", "or_load_beam",
@@ -76,6 +81,8 @@ def _p(a: Optional[np.ndarray]):
         return a.ctypes.data_as(_ip)
     if a.dtype == np.int64:
         return a.ctypes.data_as(_lp)
+    if a.dtype == np.uint64:
+        return a.ctypes.data_as(_up)
     raise TypeError(a.dtype)
 
 
@@ -179,6 +186,33 @@ def march(p, st: Dict[str, np.ndarray], jb: np.ndarray, diag: bool = False):
                           _p(st["py"]), _p(st["d0"]), _p(st["w"]), _p(st["nion"]), _p(jbc),
                           _p(fields), _p(d), _p(cnt)), "march")
     return fields, cnt, d
+
+
+def march_traj(p, st: Dict[str, np.ndarray], jb: np.ndarray, stride: int):
+    """march() recording the radius of every stride-th particle at every
+    slice; returns fields, counters and traj (n_xi, ceil(np / stride))."""
+    q = problem(p)
+    N1 = p.n_r + 1
+    n = len(st["x"])
+    fields = np.zeros((4, p.n_xi, N1))
+    traj = np.zeros((p.n_xi, (n + stride - 1) // stride))
+    cnt = np.zeros(3, dtype=np.int64)
+    jbc = np.ascontiguousarray(jb, dtype=np.float64)
+    _check(lib().or_march_traj(C.byref(q), n, _p(st["x"]), _p(st["y"]), _p(st["px"]), _p(st["py"]),
+                               _p(st["d0"]), _p(st["w"]), _p(st["nion"]), _p(jbc), _p(fields), _p(cnt),
+                               int(stride), _p(traj)), "march_traj")
+    return fields, cnt, traj
+
+
+def gain_histogram(b: Dict[str, np.ndarray], gamma_before: np.ndarray, which: int, n_bins: int,
+                   lo: float, hi: float) -> np.ndarray:
+    hist = np.zeros(n_bins + 2, dtype=np.uint64)
+    g0 = np.ascontiguousarray(gamma_before, dtype=np.float64)
+    tag = np.ascontiguousarray(b["tag"], dtype=np.int32)
+    px, py, pz = (np.ascontiguousarray(b[k], dtype=np.float64) for k in ("px", "py", "pz"))
+    _check(lib().or_gain_histogram(len(px), _p(tag), which, _p(px), _p(py), _p(pz), _p(g0), n_bins,
+                                   lo, hi, _p(hist)), "gain_histogram")
+    return hist
 
 
 def beam_push(p, b: Dict[str, np.ndarray], fields: np.ndarray, n_steps: int, dt: float) -> int:

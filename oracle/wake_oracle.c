@@ -656,10 +656,11 @@ static int64_t reflect_wall(const grid_t* g, int64_t np, double* x, double* y,
  * (RK2) steps in xi; the fields stored at slice k are those of the state at
  * xi_k; the plasma ahead of the beam (slice 0) is unperturbed.
  */
-int or_march(const or_problem* p, int64_t np,
-             double* x, double* y, double* px, double* py,
-             const double* d0, const double* w, const double* nion,
-             const double* jb, double* fields, double* diag, int64_t* counters)
+static int march_impl(const or_problem* p, int64_t np,
+                      double* x, double* y, double* px, double* py,
+                      const double* d0, const double* w, const double* nion,
+                      const double* jb, double* fields, double* diag, int64_t* counters,
+                      int32_t stride, double* traj)
 {
     if (check_problem(p) || np < 0 || !fields) return -1;
     grid_t g;
@@ -677,7 +678,13 @@ int or_march(const or_problem* p, int64_t np,
     int64_t clamps = 0, walls = 0;
     const double dxi = g.dxi;
 
+    const int64_t n_traj = stride > 0 ? (np + stride - 1) / stride : 0;
     for (int k = 0; k < p->n_xi; ++k) {
+        /* trajectories: the radius of every stride-th particle at xi_k */
+        for (int64_t q = 0; q < n_traj; ++q) {
+            const int64_t i = q * stride;
+            traj[(int64_t)k * n_traj + q] = radius_of(&g, x[i], y[i]);
+        }
         eval_core(&g, &s, np, x, y, px, py, d0, w, nion, jb + (int64_t)k * N1,
                   f0, f0 + n4, f0 + 2 * n4, f0 + 3 * n4, &clamps);
         store_fields(&g, &s, fields + (int64_t)k * N1, fields + plane + (int64_t)k * N1,
@@ -716,6 +723,24 @@ int or_march(const or_problem* p, int64_t np,
     scratch_free(&s);
     grid_free(&g);
     return 0;
+}
+
+int or_march(const or_problem* p, int64_t np,
+             double* x, double* y, double* px, double* py,
+             const double* d0, const double* w, const double* nion,
+             const double* jb, double* fields, double* diag, int64_t* counters)
+{
+    return march_impl(p, np, x, y, px, py, d0, w, nion, jb, fields, diag, counters, 0, NULL);
+}
+
+int or_march_traj(const or_problem* p, int64_t np,
+                  double* x, double* y, double* px, double* py,
+                  const double* d0, const double* w, const double* nion,
+                  const double* jb, double* fields, int64_t* counters,
+                  int32_t stride, double* traj)
+{
+    if (stride < 1 || !traj) return -1;
+    return march_impl(p, np, x, y, px, py, d0, w, nion, jb, fields, NULL, counters, stride, traj);
 }
 
 /*
@@ -815,6 +840,37 @@ double or_mean_gain(int64_t n_beam, const int32_t* tag, int32_t which,
         den += bw[i];
     }
     return den > 0.0 ? num / den : 0.0;
+}
+
+/*
+ * Energy spectrum (Section III, witness spectra): counts of the gain
+ * gamma - gamma_init in n_bins equal bins of [lo, hi), with [0] below lo and
+ * [n_bins + 1] at or above hi.  Bin k holds lo + k (hi - lo)/n_bins <= gain <
+ * lo + (k + 1)(hi - lo)/n_bins, decided as floor(n_bins (gain - lo)/(hi - lo)).
+ */
+int or_gain_histogram(int64_t n_beam, const int32_t* tag, int32_t which,
+                      const double* bpx, const double* bpy, const double* bpz,
+                      const double* gamma_before, int32_t n_bins, double lo, double hi,
+                      uint64_t* hist)
+{
+    if (n_bins < 1 || !(hi > lo) || !hist) return -1;
+    for (int32_t q = 0; q < n_bins + 2; ++q) hist[q] = 0;
+    for (int64_t i = 0; i < n_beam; ++i) {
+        if (which >= 0 && tag[i] != which) continue;
+        const double px2 = bpx[i] * bpx[i], py2 = bpy[i] * bpy[i], pz2 = bpz[i] * bpz[i];
+        const double gain = sqrt(((1.0 + px2) + py2) + pz2) - gamma_before[i];
+        if (!(gain >= lo)) {
+            ++hist[0];
+        } else if (gain >= hi) {
+            ++hist[n_bins + 1];
+        } else {
+            int k = (int)floor((gain - lo) / (hi - lo) * (double)n_bins);
+            if (k < 0) k = 0;
+            if (k > n_bins - 1) k = n_bins - 1;
+            ++hist[1 + k];
+        }
+    }
+    return 0;
 }
 
 double or_ez_peak(const or_problem* p, const double* fields, double xi_from)

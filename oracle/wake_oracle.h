@@ -91,6 +91,15 @@ int or_march(const or_problem* p, int64_t np,
              const double* d0, const double* w, const double* nion,
              const double* jb, double* fields, double* diag, int64_t* counters);
 
+/* or_march that also records, at every slice k (before its fields are
+ * computed), the radius of particles 0, stride, 2 stride, ...:
+ * traj[k * n_traj + q], n_traj = ceil(np / stride). */
+int or_march_traj(const or_problem* p, int64_t np,
+                  double* x, double* y, double* px, double* py,
+                  const double* d0, const double* w, const double* nion,
+                  const double* jb, double* fields, int64_t* counters,
+                  int32_t stride, double* traj);
+
 /* Beam advance in time with frozen fields, Eqs. (8)-(11), Boris rotation.
  * n_out counts particle-steps that sampled no field (outside the window). */
 int or_beam_push(const or_problem* p, int64_t n_beam,
@@ -102,6 +111,14 @@ int or_beam_push(const or_problem* p, int64_t n_beam,
 double or_mean_gain(int64_t n_beam, const int32_t* tag, int32_t which,
                     const double* bw, const double* gamma_before,
                     const double* bpx, const double* bpy, const double* bpz);
+
+/* Counts of gamma - gamma_before (tag == which; all if which < 0) in n_bins
+ * equal bins of [lo, hi); hist has n_bins + 2 entries: [0] below lo,
+ * [n_bins + 1] at or above hi. */
+int or_gain_histogram(int64_t n_beam, const int32_t* tag, int32_t which,
+                      const double* bpx, const double* bpy, const double* bpz,
+                      const double* gamma_before, int32_t n_bins, double lo, double hi,
+                      uint64_t* hist);
 
 /* Most negative on-axis E_z over slices with xi_k >= xi_from. */
 double or_ez_peak(const or_problem* p, const double* fields, double xi_from);

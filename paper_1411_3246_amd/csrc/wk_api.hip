@@ -171,19 +171,29 @@ wk::MarchDesc make_desc(const wk_plan* pl, const wk_plasma_bufs* b, const double
     d.group = 1;
     d.xbuf = nullptr;
     d.gctr = nullptr;
+    d.p0 = 0;
+    d.traj = nullptr;
+    d.traj_n = 0;
+    d.traj_stride = 0;
     return d;
 }
 
 // One response from a march region at `ws` laid out for `layout_group`
 // workgroups (at least the group that marches it).
 wk_status response_in(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb, void* d_fields,
-                      char* ws, int layout_group, uint64_t* d_counters, hipStream_t s)
+                      char* ws, int layout_group, uint64_t* d_counters, hipStream_t s, double* traj = nullptr,
+                      int traj_stride = 0)
 {
     const int G = single_group(plan);
     const int shape = wk::pick_shape(member_np(plan, G), plan->threads, plan->N1, plan->p.prec, G);
     wk::MarchLaunch L{};
     L.one = make_desc(plan, plasma, d_jb, d_fields, d_counters);
     L.one.group = G;
+    if (traj) {
+        L.one.traj = traj;
+        L.one.traj_stride = traj_stride;
+        L.one.traj_n = (plan->np + traj_stride - 1) / traj_stride;
+    }
     L.one.xbuf = (double*)(ws + march_grow_bytes(plan, layout_group));
     L.one.gctr = (unsigned*)(ws + march_grow_bytes(plan, layout_group) + march_xbuf_bytes(plan->N1, layout_group));
     L.grow = plan->big ? (double*)ws : nullptr;
@@ -414,6 +424,21 @@ wk_status wk_plasma_response(const wk_plan* plan, const wk_plasma_bufs* plasma, 
     if (st != WK_OK) return st;
     return response_in(plan, plasma, d_jb, d_fields, (char*)d_workspace, wk::kMaxGroup, d_counters,
                        (hipStream_t)stream);
+}
+
+wk_status wk_plasma_response_traj(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb,
+                                  void* d_fields, void* d_workspace, int32_t stride, double* d_traj,
+                                  uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_jb || !d_fields || !d_workspace || !d_traj || !d_counters)
+        return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (stride < 1) return fail(WK_ERR_INVALID_ARG, "stride must be >= 1 (got %d)", stride);
+    if (plan->p.prec != WK_FP64) return fail(WK_ERR_UNSUPPORTED, "trajectories are recorded by FP64 plans only");
+    if (!aligned8(d_traj)) return fail(WK_ERR_BUFFER, "trajectory buffer is not 8-byte aligned");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
+    return response_in(plan, plasma, d_jb, d_fields, (char*)d_workspace, wk::kMaxGroup, d_counters,
+                       (hipStream_t)stream, d_traj, stride);
 }
 
 wk_status wk_plasma_response_noalloc(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb,
@@ -738,6 +763,20 @@ wk_status wk_mean_gain(const wk_plan* plan, const wk_beam_bufs* beam, int32_t wh
     return hip_status(wk::launch_mean_gain(plan->p.n_beam, *beam, which, d_out, (char*)d_workspace + off,
                                            (hipStream_t)stream),
                       "mean gain");
+}
+
+wk_status wk_gain_histogram(const wk_plan* plan, const wk_beam_bufs* beam, int32_t which, int32_t n_bins,
+                            double lo, double hi, uint64_t* d_hist, void* stream)
+{
+    if (!plan || !d_hist) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (n_bins < 1 || n_bins > 4096) return fail(WK_ERR_INVALID_ARG, "n_bins must be in [1, 4096] (got %d)", n_bins);
+    if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+        return fail(WK_ERR_INVALID_ARG, "the range needs finite lo < hi");
+    wk_status st = check_beam(plan, beam);
+    if (st != WK_OK) return st;
+    return hip_status(wk::launch_gain_hist(plan->p.n_beam, *beam, which, n_bins, lo, hi,
+                                           (unsigned long long*)d_hist, (hipStream_t)stream),
+                      "gain histogram");
 }
 
 wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from, double* d_out, void* stream)

@@ -1,4 +1,6 @@
 // Loaders, beam current, beam push and diagnostics.
+#include <algorithm>
+
 #include "wk_beam_dev.h"
 
 namespace wk {
@@ -375,6 +377,43 @@ __global__ void k_gain_final(const double* part, int nb, double* out)
     out[0] = den > 0.0 ? num / den : 0.0;
 }
 
+// Energy spectrum: counts of gamma - gamma_init in n_bins equal bins of
+// [lo, hi), with an underflow (index 0) and an overflow (n_bins + 1) bin.
+// The bin of a particle is decided in double with every operation rounded on
+// its own (no contracted multiply-adds), as a plain C evaluation decides it;
+// integer counts make the result independent of the order of the adds.
+constexpr int kHistMax = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_gain_hist(int64_t n, wk_beam_bufs b, int which, int n_bins,
+                                                      double lo, double hi, unsigned long long* hist)
+{
+#pragma clang fp contract(off)
+    __shared__ unsigned int h[kHistMax + 2];
+    for (int q = threadIdx.x; q < n_bins + 2; q += blockDim.x) h[q] = 0u;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (which >= 0 && b.d_tag[i] != which) continue;
+        const double px = b.d_px[i], py = b.d_py[i], pz = b.d_pz[i];
+        const double px2 = px * px, py2 = py * py, pz2 = pz * pz;
+        const double gain = sqrt(((1.0 + px2) + py2) + pz2) - b.d_gamma_init[i];
+        int q;
+        if (!(gain >= lo)) {
+            q = 0;
+        } else if (gain >= hi) {
+            q = n_bins + 1;
+        } else {
+            const double u = (gain - lo) / (hi - lo);
+            int k = (int)floor(u * (double)n_bins);
+            k = k < 0 ? 0 : (k > n_bins - 1 ? n_bins - 1 : k);
+            q = 1 + k;
+        }
+        atomicAdd(h + q, 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_bins + 2; q += blockDim.x)
+        if (h[q]) atomicAdd(hist + q, (unsigned long long)h[q]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_ez_peak(GridDesc g, const R* fields, double xi_from,
                                                     double* out)
@@ -551,6 +590,18 @@ hipError_t launch_mean_gain(int64_t n_beam, const wk_beam_bufs& b, int which, do
     double* part = (double*)ws;
     hipLaunchKernelGGL(k_gain_partial, dim3(kGainBlocks), dim3(kBlock), 0, s, n_beam, b, which, part);
     hipLaunchKernelGGL(k_gain_final, dim3(1), dim3(64), 0, s, part, kGainBlocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gain_hist(int64_t n_beam, const wk_beam_bufs& b, int which, int n_bins, double lo, double hi,
+                            unsigned long long* hist, hipStream_t s)
+{
+    if (n_bins < 1 || n_bins > kHistMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kBlock), 0, s, hist, (int64_t)n_bins + 2);
+    if (n_beam > 0) {
+        const int blocks = (int)std::min<int64_t>(1024, (n_beam + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_gain_hist, dim3(blocks), dim3(kBlock), 0, s, n_beam, b, which, n_bins, lo, hi, hist);
+    }
     return hipGetLastError();
 }
 

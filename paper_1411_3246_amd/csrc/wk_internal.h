@@ -35,6 +35,10 @@ struct MarchDesc {
     int32_t group;       // workgroups that march this response together (1..kMaxGroup)
     double* xbuf;        // group > 1: partial deposit rows, [2][group][kXRows][stride] doubles (zeroed)
     unsigned int* gctr;  // group > 1: arrival counter of the group barrier (own 256-byte line)
+    int64_t p0;          // index of this descriptor's first particle in the response
+    double* traj;        // optional: radius of every traj_stride-th particle per slice,
+    int64_t traj_n;      //   [n_xi][traj_n] doubles, traj_n = ceil(np_response / traj_stride)
+    int32_t traj_stride;
 };
 
 // Largest number of workgroups marching one response.
@@ -145,6 +149,8 @@ hipError_t launch_beam_push(const GridDesc& g, int64_t n_beam, const wk_beam_buf
                             unsigned long long* counters, hipStream_t s);
 hipError_t launch_mean_gain(int64_t n_beam, const wk_beam_bufs& b, int which, double* out,
                             void* ws, hipStream_t s);
+hipError_t launch_gain_hist(int64_t n_beam, const wk_beam_bufs& b, int which, int n_bins, double lo, double hi,
+                            unsigned long long* hist, hipStream_t s);
 hipError_t launch_ez_peak(const GridDesc& g, const void* fields, int prec, double xi_from,
                           double* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -25,6 +25,7 @@ __device__ __forceinline__ MarchDesc member_desc(const MarchDesc& full, int rank
     const int c1 = (int)((int64_t)full.n_r * (rank + 1) / G);
     const int64_t p0 = (int64_t)c0 * full.ppc;
     MarchDesc d = full;
+    d.p0 = full.p0 + p0;
     d.np = (int64_t)(c1 - c0) * full.ppc;
     d.x = full.x + p0;
     d.px = full.px + p0;
@@ -47,7 +48,7 @@ __device__ __forceinline__ dev::Group member_group(const MarchDesc& full, int ra
     return grp;
 }
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS>
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS, bool TRAJ = false>
 __global__ __launch_bounds__(T, WPS) void k_march(MarchLaunch L)
 {
     extern __shared__ double smem[];
@@ -69,7 +70,10 @@ __global__ __launch_bounds__(T, WPS) void k_march(MarchLaunch L)
         d.grow = BIG ? L.grow + (int64_t)blockIdx.x * BIG_ROWS * L.grow_stride : nullptr;
         void* pconst = BIG ? nullptr : (void*)(smem + NUM_ROWS * lds_stride(full.n_r + 1));
         M m(d, smem, pconst, member_group<R>(full, rank), rank == 0, true);
-        m.run();
+        if constexpr (TRAJ)
+            m.run_traj();
+        else
+            m.run();
         if (!L.descs) break;
         __syncthreads();
     }
@@ -84,6 +88,15 @@ hipError_t go(const MarchLaunch& L, int grid, size_t lds, hipStream_t s, int* oc
         return hipErrorInvalidValue;
     } else {
         auto kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd>;
+        if (L.one.traj) {
+            // particle radii recorded: an FP64 single response only
+            if constexpr (sizeof(R) == 8) {
+                if (L.descs || occ) return hipErrorInvalidValue;
+                kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd, true>;
+            } else {
+                return hipErrorInvalidValue;
+            }
+        }
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, S.threads, lds);

@@ -1011,6 +1011,8 @@ struct Marcher {
         // true: the moment rows J_z, M1..M5 are kept (for before_b) instead of
         // being folded into the right-hand side of the B_theta equation
         static constexpr bool kKeepMoments = false;
+        // true: the radii of every traj_stride-th particle are stored per slice
+        static constexpr bool kTraj = false;
         __device__ __forceinline__ void before_b(Marcher&, int, int) {}
         __device__ __forceinline__ void after_b(Marcher&, int, int, const double*) {}
         // extra raw J_z deposits (before the exchange) at slice k
@@ -1050,6 +1052,16 @@ struct Marcher {
     __device__ __forceinline__ void run()
     {
         GlobalJb hooks;
+        run(hooks);
+    }
+
+    // The march with the particle radii recorded (diagnostic variant).
+    struct TrajJb : GlobalJb {
+        static constexpr bool kTraj = true;
+    };
+    __device__ __forceinline__ void run_traj()
+    {
+        TrajJb hooks;
         run(hooks);
     }
 
@@ -1106,6 +1118,19 @@ struct Marcher {
         sync();
     }
 
+    // Radius of every traj_stride-th particle of the response at slice k
+    // (the state Y_k the slice's fields are computed from).
+    __device__ __forceinline__ void record_radii(int k)
+    {
+        for_idx([&](int64_t i, const Part<R>& p) {
+            const int64_t gi = d.p0 + i;
+            if (gi % d.traj_stride == 0) {
+                const double r = (GEOM == WK_CYL && WARM) ? sqrt(p.x * p.x + p.y * p.y) : fabs(p.x);
+                d.traj[(int64_t)k * d.traj_n + gi / d.traj_stride] = r;
+            }
+        });
+    }
+
     template <class Hooks>
     __device__ __forceinline__ void run(Hooks& hooks)
     {
@@ -1151,6 +1176,7 @@ struct Marcher {
         }
         exchange<1, kRowS>();
         for (int k = 0; k < d.n_xi; ++k) {
+            if constexpr (Hooks::kTraj) record_radii(k);
             hooks.before_slice(*this, k);
             const double* jb0 = hooks.jb_row(*this, k);
             // ---- stage 1 at (Y_k, xi_k): psi -> moments -> E_z, B ----

@@ -68,7 +68,7 @@ EXPORTS = [
     "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle", "wk_plan_set_group", "wk_plan_group", "wk_cycle_group",
-    "wk_plasma_response_noalloc",
+    "wk_plasma_response_noalloc", "wk_plasma_response_traj", "wk_gain_histogram",
     "wk_gradient_workspace_size", "wk_gradient_forward", "wk_gradient_backward",
 ]
 
@@ -113,6 +113,8 @@ def lib():
     L.wk_beam_current.argtypes = [vp, C.POINTER(WkBeamBufs), vp, vp, vp, vp]
     L.wk_plasma_response.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp, vp]
     L.wk_plasma_response_noalloc.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp]
+    L.wk_plasma_response_traj.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, i32, vp, vp, vp]
+    L.wk_gain_histogram.argtypes = [vp, C.POINTER(WkBeamBufs), i32, i32, d, d, vp, vp]
     L.wk_batch_desc_bytes.argtypes = [i32]
     L.wk_batch_desc_bytes.restype = C.c_size_t
     L.wk_batch_workspace_size.argtypes = [i32, C.POINTER(vp)]
@@ -295,6 +297,20 @@ class Plan:
                                         _ptr(workspace), _ptr(counters), _stream(stream)),
                "wk_plasma_response")
 
+    def plasma_response_traj(self, plasma: Dict, jb, fields, workspace, stride: int, traj, counters,
+                             stream=None):
+        """wk_plasma_response recording the radius of every stride-th particle per slice."""
+        b = self.plasma_bufs(plasma)
+        _check(lib().wk_plasma_response_traj(self.handle, C.byref(b), _ptr(jb), _ptr(fields), _ptr(workspace),
+                                             int(stride), _ptr(traj), _ptr(counters), _stream(stream)),
+               "wk_plasma_response_traj")
+
+    def gain_histogram(self, beam: Dict, which: int, n_bins: int, lo: float, hi: float, hist, stream=None):
+        """Counts of gamma - gamma_init in n_bins bins of [lo, hi) (+ under/overflow)."""
+        b = self.beam_bufs(beam)
+        _check(lib().wk_gain_histogram(self.handle, C.byref(b), int(which), int(n_bins), float(lo), float(hi),
+                                       _ptr(hist), _stream(stream)), "wk_gain_histogram")
+
     def plasma_response_noalloc(self, plasma: Dict, jb, fields, counters, stream=None):
         """wk_plasma_response with the library's static scratch in place of a workspace."""
         b = self.plasma_bufs(plasma)
@@ -431,6 +447,25 @@ class Simulation:
         """Load the plasma ahead of the beam and march it through the window."""
         self.plan.init_plasma(self.plasma, self.plasma_draws)
         self.plan.plasma_response(self.plasma, self.jb, self.fields, self.workspace, self.counters)
+
+    def response_traj(self, stride: int):
+        """response() recording the radius of every stride-th plasma particle per
+        slice; returns the (n_xi, ceil(n_plasma / stride)) tensor."""
+        import torch
+        n = (self.problem.n_plasma + stride - 1) // stride
+        traj = torch.zeros((self.problem.n_xi, n), dtype=torch.float64, device=self.jb.device)
+        self.plan.init_plasma(self.plasma, self.plasma_draws)
+        self.plan.plasma_response_traj(self.plasma, self.jb, self.fields, self.workspace, stride, traj,
+                                       self.counters)
+        return traj
+
+    def gain_histogram(self, which: int, n_bins: int, lo: float, hi: float):
+        """Energy spectrum of the beam (tag == which; all if which < 0): counts
+        in n_bins bins of [lo, hi) with under/overflow at both ends."""
+        import torch
+        hist = torch.zeros(n_bins + 2, dtype=torch.int64, device=self.jb.device)
+        self.plan.gain_histogram(self.beam, which, n_bins, lo, hi, hist)
+        return hist
 
     def response_noalloc(self):
         """response() through the allocation-free entry point."""

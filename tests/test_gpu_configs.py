@@ -200,16 +200,18 @@ def test_forced_d_clamp(O, W, n_xi):
     """A drive of 60 n_p expels the plasma so hard that D = gamma - p_z of
     some particles reaches the floor d_min: 3 clamped evaluations at 240
     slices, 1279 at the coarser 120.  The clamp counts equal the oracle's.
-    Near the floor the response is ill-conditioned (terms in 1/D^3; at 240
-    slices the oracle's own fields move by tens of percent at the end of the
-    window under a 1-ulp change), so the fields are held slice by slice to
-    a multiple of the oracle's own spread (1-ulp and summation-order changes)
-    plus 1e-10 of each field's scale, and at 240 slices to 1e-10 of the
-    scale up to eight slices before the first clamp.  The spread factor is
-    100 here, not 10: the GPU's rounding differences enter at every slice,
-    the oracle's spread comes from one change, and at the floor the
-    amplification is largest (measured: 31 x the spread at 240 slices,
-    1.7 x at 120)."""
+
+    Near the floor the response is ill-conditioned (terms in 1/D^3).
+    * At 240 slices it turns chaotic after the first clamp: the oracle's own
+      fields move by 22-75 % of their scale under a 1-ulp change of the
+      initial radii.  So the fields are compared within 1e-10 of each field's
+      scale up to eight slices before the first clamp, and after it only the
+      counts and finiteness are compared.
+    * At 120 slices the fields are held slice by slice to 100 times the
+      oracle's own spread (1-ulp and summation-order changes) plus 1e-10 of
+      the scale.  The factor is 100, not 10: the GPU's rounding differences
+      enter at every slice, the oracle's spread comes from one change (the
+      measured error is 17 times the spread)."""
     p = inputs.facet_two_bunch(n_r=32, n_xi=n_xi, ppc=2, u_th=0.0, n_d=60.0, r_max=3.0, n_beam=0,
                                prec="fp64", name=f"d-clamp-{n_xi}")
     print(f"case {p.name}", flush=True)
@@ -220,12 +222,14 @@ def test_forced_d_clamp(O, W, n_xi):
     print("clamps gpu / oracle:", c["d_clamp"], int(c0[0]), flush=True)
     assert c["nonfinite"] == 0
     assert c["d_clamp"] == int(c0[0])
-    _check_envelope(f0, env, sim, factor=100.0)
+    f = _np(sim.fields)
+    assert np.all(np.isfinite(f))
     if n_xi == 240:
         k_first = _first_clamped_slice(O, p, jb)
-        f = _np(sim.fields)
         for i in range(4):
             assert _rel(f[i, :k_first - 8], f0[i, :k_first - 8]) <= 1e-10, i
+    else:
+        _check_envelope(f0, env, sim, factor=100.0)
 
 
 def _first_clamped_slice(O, p, jb):

@@ -423,6 +423,48 @@ def test_ez_peak_prescribed_field(O):
     assert O.ez_peak(p, fields, -1.0) == -5.0
 
 
+def test_trajectory_recording_is_the_state(O):
+    """The recorded trajectories are the particle radii of the march itself:
+    the fields equal those of the plain march bit for bit, row 0 holds the
+    loaded radii and the last row the radii of the final state, for every
+    stride-th particle."""
+    for geom in ("cyl", "slab"):
+        p = inputs.facet_two_bunch(n_r=24, n_xi=50, ppc=4, u_th=0.02, n_d=1.0, n_beam=0, prec="fp64",
+                                   geom=geom, r_max=6.0 if geom == "cyl" else 8.0)
+        st = O.load_plasma(p, inputs.plasma_draws(p))
+        jb = O.beam_current_analytic(p)
+        f0, c0, _ = O.march(p, {k: v.copy() for k, v in st.items()}, jb)
+        s1 = {k: v.copy() for k, v in st.items()}
+        f1, c1, tr = O.march_traj(p, s1, jb, 7)
+        assert np.array_equal(f0, f1) and np.array_equal(c0, c1)
+        assert tr.shape == (p.n_xi, (p.n_plasma + 6) // 7)
+
+        def rad(s):
+            return np.sqrt(s["x"] * s["x"] + s["y"] * s["y"]) if geom == "cyl" else np.abs(s["x"])
+        assert np.array_equal(tr[0], rad(st)[::7])
+        assert np.array_equal(tr[-1], rad(s1)[::7])
+
+
+def test_gain_histogram_is_numpy_histogram(O):
+    """The oracle's energy spectrum equals numpy.histogram of the same gains
+    over the same range (under- and overflow counted apart), per tag and for
+    all particles."""
+    rng = np.random.default_rng(7)
+    n = 20000
+    b = {"tag": rng.integers(0, 2, n).astype(np.int32), "px": rng.normal(0.0, 3.0, n),
+         "py": rng.normal(0.0, 3.0, n), "pz": rng.uniform(500.0, 1500.0, n)}
+    g0 = rng.uniform(900.0, 1100.0, n)
+    gain = np.sqrt(1 + b["px"] ** 2 + b["py"] ** 2 + b["pz"] ** 2) - g0
+    for which in (-1, 0, 1):
+        sel = np.ones(n, bool) if which < 0 else b["tag"] == which
+        for n_bins, lo, hi in ((50, -400.0, 400.0), (7, -100.0, 250.0)):
+            h = O.gain_histogram(b, g0, which, n_bins, lo, hi)
+            ref, _ = np.histogram(gain[sel], bins=n_bins, range=(lo, hi))
+            assert np.array_equal(h[1:-1], ref), (which, n_bins)
+            assert h[0] == np.sum(gain[sel] < lo) and h[-1] == np.sum(gain[sel] >= hi)
+            assert int(h.sum()) == int(sel.sum())
+
+
 def test_beam_loader_and_current(O):
     """Beam macroparticles reproduce the charge of Eq. (12) and the deposit
     conserves it."""
