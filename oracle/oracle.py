@@ -57,6 +57,8 @@ def lib():
         L.or_mean_gain.argtypes = [C.c_int64, _ip, C.c_int32, _dp, _dp, _dp, _dp, _dp]
         L.or_mean_gain.restype = C.c_double
         L.or_ez_peak.argtypes = [P, _dp, C.c_double]
+        L.or_march_direct.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _lp,
+                                      C.c_int32, C.c_double, _ip]
         L.or_march_traj.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _lp,
                                     C.c_int32, _dp]
         L.or_gain_histogram.argtypes = [C.c_int64, _ip, C.c_int32, _dp, _dp, _dp, _dp, C.c_int32,
@@ -202,6 +204,22 @@ def march_traj(p, st: Dict[str, np.ndarray], jb: np.ndarray, stride: int):
                                _p(st["d0"]), _p(st["w"]), _p(st["nion"]), _p(jbc), _p(fields), _p(cnt),
                                int(stride), _p(traj)), "march_traj")
     return fields, cnt, traj
+
+
+def march_direct(p, st: Dict[str, np.ndarray], jb: np.ndarray, iters: int = 8, tol: float = 1e-10):
+    """The response with B_theta from Eq. (6) directly (implicit d_xi E_z,
+    Newton-GMRES per slice); returns fields, counters and the Newton steps
+    used per slice."""
+    q = problem(p)
+    N1 = p.n_r + 1
+    fields = np.zeros((4, p.n_xi, N1))
+    cnt = np.zeros(3, dtype=np.int64)
+    its = np.zeros(p.n_xi, dtype=np.int32)
+    jbc = np.ascontiguousarray(jb, dtype=np.float64)
+    _check(lib().or_march_direct(C.byref(q), len(st["x"]), _p(st["x"]), _p(st["y"]), _p(st["px"]),
+                                 _p(st["py"]), _p(st["d0"]), _p(st["w"]), _p(st["nion"]), _p(jbc), _p(fields),
+                                 _p(cnt), int(iters), float(tol), _p(its)), "march_direct")
+    return fields, cnt, its
 
 
 def gain_histogram(b: Dict[str, np.ndarray], gamma_before: np.ndarray, which: int, n_bins: int,

@@ -446,11 +446,28 @@ static radial_t radial_of(const grid_t* g, double x, double y, double px, double
     return q;
 }
 
+static int eval_core_b(const grid_t* g, scratch_t* s, int64_t np,
+                       const double* x, const double* y, const double* px, const double* py,
+                       const double* d0, const double* w, const double* nion,
+                       const double* jb_row, double* fx, double* fy, double* fpx, double* fpy,
+                       int64_t* clamps, const double* b_given);
+
 static int eval_core(const grid_t* g, scratch_t* s, int64_t np,
                      const double* x, const double* y, const double* px, const double* py,
                      const double* d0, const double* w, const double* nion,
                      const double* jb_row, double* fx, double* fy, double* fpx, double* fpy,
                      int64_t* clamps)
+{
+    return eval_core_b(g, s, np, x, y, px, py, d0, w, nion, jb_row, fx, fy, fpx, fpy, clamps, NULL);
+}
+
+/* The stage evaluation; with b_given != NULL, B_theta is taken from it
+ * instead of the Helmholtz solve of step 7 (the Eq. (6)-direct march). */
+static int eval_core_b(const grid_t* g, scratch_t* s, int64_t np,
+                       const double* x, const double* y, const double* px, const double* py,
+                       const double* d0, const double* w, const double* nion,
+                       const double* jb_row, double* fx, double* fy, double* fpx, double* fpy,
+                       int64_t* clamps, const double* b_given)
 {
     const int N = g->N;
     const double h = g->h, a = g->alpha;
@@ -502,6 +519,10 @@ static int eval_core(const grid_t* g, scratch_t* s, int64_t np,
      * 1..N-1, B_0 = 0.  At the wall E_z = 0 for every xi, so Eq. (6) there
      * reads (1/r) d_r (r B) = J_z; it closes the system at node N
      * (discretized at r_{N-1/2}). */
+    if (b_given) {
+        memcpy(s->B, b_given, sizeof(double) * (N + 1));
+        goto derivative;
+    }
     const double h2 = h * h;
     for (int j = 1; j < N; ++j) {
         const double rj = g->rn[j];
@@ -527,6 +548,7 @@ static int eval_core(const grid_t* g, scratch_t* s, int64_t np,
     or_thomas(N, s->ta, s->tb, s->tc, s->td, s->tx);
     s->B[0] = 0.0;
     for (int j = 1; j <= N; ++j) s->B[j] = s->tx[j - 1];
+derivative:
 
     /* 8. xi-derivatives of the particle state: Eq. (5) and Eq. (4) (the
      * centrifugal term of Eq. (4) is the polar form of free Cartesian
@@ -741,6 +763,272 @@ int or_march_traj(const or_problem* p, int64_t np,
 {
     if (stride < 1 || !traj) return -1;
     return march_impl(p, np, x, y, px, py, d0, w, nion, jb, fields, NULL, counters, stride, traj);
+}
+
+/*
+ * B_theta from Eq. (6) as written: (1/r) d_r (r B) = d_xi E_z + J_z, with
+ * d_xi E_z = d^2 psi / d xi^2 (Eq. (7) fixes E_z = d_xi psi in the gauge of
+ * the psi solve), integrated from the axis by the trapezoid rule:
+ * r_j B_j = r_{j-1} B_{j-1} + h/2 (r_{j-1} q_{j-1} + r_j q_j), B_0 = 0
+ * (slab: without the r weights).
+ */
+static void b_direct(const grid_t* g, const double* dez, const double* jz, double* b)
+{
+    const int N = g->N;
+    const double h = g->h;
+    b[0] = 0.0;
+    if (g->p->geom == OR_CYL) {
+        double rb = 0.0;
+        for (int j = 1; j <= N; ++j) {
+            rb += 0.5 * h * (g->rn[j - 1] * (dez[j - 1] + jz[j - 1]) + g->rn[j] * (dez[j] + jz[j]));
+            b[j] = rb / g->rn[j];
+        }
+    } else {
+        for (int j = 1; j <= N; ++j) b[j] = b[j - 1] + 0.5 * h * ((dez[j - 1] + jz[j - 1]) + (dez[j] + jz[j]));
+    }
+}
+
+/* Workspace of the Eq. (6)-direct march. */
+typedef struct {
+    const grid_t* g;
+    scratch_t* s;
+    int64_t np, n4;
+    const double *x, *y, *px, *py, *d0, *w, *nion, *jb_k, *jb_n;
+    const double *ez_prev, *ez_k, *jz_k;
+    double *f0, *f1, *ys, *yn, *dez, *bstar;
+    int last;
+    int64_t scratch_clamps;
+} direct_t;
+
+/* One trial step of slice k with B_k = b: the Heun step from Y_k (stage-2 B
+ * at the predicted state from Eq. (6) with the one-sided d_xi E_z), E_z of
+ * the stepped state, and the B_k that Eq. (6) gives with
+ * d_xi E_z = (E_z,k+1 - E_z,k) / dxi (the last slice: (E_z,k - E_z,k-1) /
+ * dxi); written to out.  The stepped state is left in yn. */
+static void direct_phi(direct_t* c, const double* b, double* out)
+{
+    const grid_t* g = c->g;
+    scratch_t* s = c->s;
+    const int N = g->N;
+    const int64_t np = c->np, n4 = c->n4;
+    const double dxi = g->dxi, hd = 0.5 * dxi;
+    double *f0 = c->f0, *f1 = c->f1, *ys = c->ys, *yn = c->yn;
+    eval_core_b(g, s, np, c->x, c->y, c->px, c->py, c->d0, c->w, c->nion, c->jb_k, f0, f0 + n4, f0 + 2 * n4,
+                f0 + 3 * n4, &c->scratch_clamps, b);
+    for (int64_t i = 0; i < np; ++i) {
+        ys[i] = c->x[i] + dxi * f0[i];
+        ys[n4 + i] = c->y[i] + dxi * f0[n4 + i];
+        ys[2 * n4 + i] = c->px[i] + dxi * f0[2 * n4 + i];
+        ys[3 * n4 + i] = c->py[i] + dxi * f0[3 * n4 + i];
+    }
+    eval_core_b(g, s, np, ys, ys + n4, ys + 2 * n4, ys + 3 * n4, c->d0, c->w, c->nion, c->jb_n, NULL, NULL, NULL,
+                NULL, &c->scratch_clamps, b);
+    for (int j = 0; j <= N; ++j) c->dez[j] = (s->Ez[j] - c->ez_k[j]) / dxi;
+    b_direct(g, c->dez, s->Jz, c->bstar);
+    eval_core_b(g, s, np, ys, ys + n4, ys + 2 * n4, ys + 3 * n4, c->d0, c->w, c->nion, c->jb_n, f1, f1 + n4,
+                f1 + 2 * n4, f1 + 3 * n4, &c->scratch_clamps, c->bstar);
+    for (int64_t i = 0; i < np; ++i) {
+        yn[i] = c->x[i] + hd * (f0[i] + f1[i]);
+        yn[n4 + i] = c->y[i] + hd * (f0[n4 + i] + f1[n4 + i]);
+        yn[2 * n4 + i] = c->px[i] + hd * (f0[2 * n4 + i] + f1[2 * n4 + i]);
+        yn[3 * n4 + i] = c->py[i] + hd * (f0[3 * n4 + i] + f1[3 * n4 + i]);
+    }
+    if (c->last) {
+        for (int j = 0; j <= N; ++j) c->dez[j] = (c->ez_k[j] - c->ez_prev[j]) / dxi;
+    } else {
+        eval_core_b(g, s, np, yn, yn + n4, yn + 2 * n4, yn + 3 * n4, c->d0, c->w, c->nion, c->jb_n, NULL, NULL,
+                    NULL, NULL, &c->scratch_clamps, b);
+        for (int j = 0; j <= N; ++j) c->dez[j] = (s->Ez[j] - c->ez_k[j]) / dxi;
+    }
+    b_direct(g, c->dez, c->jz_k, out);
+}
+
+/*
+ * The plasma response with B_theta from Eq. (6) directly instead of the
+ * Helmholtz form.  d_xi E_z at slice k is taken implicitly, (E_z,k+1 -
+ * E_z,k) / dxi, and E_z of slice k + 1 depends on B_k through the step, so
+ * B_k solves B = Phi(B) with Phi the trial step of direct_phi.
+ * * Plain iteration of Phi diverges: a change of B bends the orbits by
+ *   B dxi and moves E_z,k+1 by about B dxi r_max, which the difference
+ *   divides by dxi, a gain of order r_max for any dxi.  So the fixed point
+ *   is found by Newton steps on B - Phi(B) = 0, each solving its linear
+ *   system by GMRES (Saad and Schultz 1986) with the Jacobian applied by a
+ *   finite difference of Phi: at most `iters` Newton steps, until the
+ *   residual is at most tol of max |B|.
+ * * The centred difference (E_z,k+1 - E_z,k-1) / (2 dxi) couples alternate
+ *   slices and grows an odd-even mode from slice to slice; the one-sided
+ *   implicit difference is stable and first order in dxi.
+ * Slice 0 (unperturbed plasma ahead of the beam) starts from B = 0.
+ * iterations[k] receives the Newton steps used.
+ */
+#define DIRECT_KRYLOV 40
+
+static double vnorm(const double* v, int n)
+{
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += v[i] * v[i];
+    return sqrt(s2);
+}
+
+/* Solve (I - J) dx = r with J v = (Phi(b + eps v) - phi_b) / eps by GMRES;
+ * V: (m + 1) n, H: (m + 1) m. */
+static void direct_gmres(direct_t* c, const double* b, const double* phi_b, const double* r, double* dx, int n,
+                         double* V, double* H, double* work, double* tmp)
+{
+    const int m = DIRECT_KRYLOV;
+    double cs[DIRECT_KRYLOV], sn[DIRECT_KRYLOV], gv[DIRECT_KRYLOV + 1], yv[DIRECT_KRYLOV];
+    for (int i = 0; i < n; ++i) dx[i] = 0.0;
+    const double beta = vnorm(r, n);
+    if (beta == 0.0) return;
+    for (int i = 0; i < n; ++i) V[i] = r[i] / beta;
+    for (int i = 0; i <= m; ++i) gv[i] = 0.0;
+    gv[0] = beta;
+    const double bn = vnorm(b, n);
+    int k_used = 0;
+    for (int k = 0; k < m; ++k) {
+        double* vk = V + (int64_t)k * n;
+        double* w = V + (int64_t)(k + 1) * n;
+        /* w = (I - J) v_k */
+        const double eps = 1e-7 * (1.0 + bn);
+        for (int i = 0; i < n; ++i) tmp[i] = b[i] + eps * vk[i];
+        direct_phi(c, tmp, work);
+        for (int i = 0; i < n; ++i) w[i] = vk[i] - (work[i] - phi_b[i]) / eps;
+        for (int q = 0; q <= k; ++q) {
+            const double* vq = V + (int64_t)q * n;
+            double hq = 0.0;
+            for (int i = 0; i < n; ++i) hq += w[i] * vq[i];
+            H[q * m + k] = hq;
+            for (int i = 0; i < n; ++i) w[i] -= hq * vq[i];
+        }
+        const double hn = vnorm(w, n);
+        H[(k + 1) * m + k] = hn;
+        if (hn > 0.0)
+            for (int i = 0; i < n; ++i) w[i] /= hn;
+        for (int q = 0; q < k; ++q) {
+            const double a0 = H[q * m + k], a1 = H[(q + 1) * m + k];
+            H[q * m + k] = cs[q] * a0 + sn[q] * a1;
+            H[(q + 1) * m + k] = -sn[q] * a0 + cs[q] * a1;
+        }
+        const double a0 = H[k * m + k], a1 = H[(k + 1) * m + k];
+        const double den = sqrt(a0 * a0 + a1 * a1);
+        cs[k] = den > 0.0 ? a0 / den : 1.0;
+        sn[k] = den > 0.0 ? a1 / den : 0.0;
+        H[k * m + k] = den;
+        H[(k + 1) * m + k] = 0.0;
+        gv[k + 1] = -sn[k] * gv[k];
+        gv[k] = cs[k] * gv[k];
+        k_used = k + 1;
+        if (fabs(gv[k + 1]) <= 1e-13 * beta || hn == 0.0) break;
+    }
+    for (int k = k_used - 1; k >= 0; --k) {
+        double t = gv[k];
+        for (int q = k + 1; q < k_used; ++q) t -= H[k * m + q] * yv[q];
+        yv[k] = t / H[k * m + k];
+    }
+    for (int k = 0; k < k_used; ++k)
+        for (int i = 0; i < n; ++i) dx[i] += yv[k] * V[(int64_t)k * n + i];
+}
+
+int or_march_direct(const or_problem* p, int64_t np,
+                    double* x, double* y, double* px, double* py,
+                    const double* d0, const double* w, const double* nion,
+                    const double* jb, double* fields, int64_t* counters,
+                    int32_t iters, double tol, int32_t* iterations)
+{
+    if (check_problem(p) || np < 0 || !fields || iters < 1) return -1;
+    grid_t g;
+    scratch_t s;
+    int rc = grid_init(p, &g);
+    if (!rc) rc = scratch_init(&s, g.N, np);
+    if (rc) { grid_free(&g); return -2; }
+    const int N = g.N, N1 = N + 1;
+    const int64_t plane = (int64_t)p->n_xi * N1;
+    const int64_t n4 = np > 0 ? np : 1;
+    const int m = DIRECT_KRYLOV;
+    double* f0 = (double*)malloc(sizeof(double) * 4 * n4);
+    double* f1 = (double*)malloc(sizeof(double) * 4 * n4);
+    double* ys = (double*)malloc(sizeof(double) * 4 * n4);
+    double* yn = (double*)malloc(sizeof(double) * 4 * n4);
+    double* rows = (double*)malloc(sizeof(double) * 12 * N1);
+    double* V = (double*)malloc(sizeof(double) * (m + 1) * N1);
+    double* H = (double*)malloc(sizeof(double) * (m + 1) * m);
+    if (!f0 || !f1 || !ys || !yn || !rows || !V || !H) {
+        free(f0); free(f1); free(ys); free(yn); free(rows); free(V); free(H);
+        scratch_free(&s); grid_free(&g);
+        return -2;
+    }
+    double* ez_prev = rows;
+    double* ez_k = rows + N1;
+    double* jz_k = rows + 2 * N1;
+    double* bk = rows + 3 * N1;
+    double* phi = rows + 4 * N1;
+    double* res = rows + 5 * N1;
+    double* dx = rows + 6 * N1;
+    double* work = rows + 7 * N1;
+    double* tmp = rows + 8 * N1;
+    double* dez = rows + 9 * N1;
+    double* bstar = rows + 10 * N1;
+    double* psi_k = rows + 11 * N1;
+    for (int j = 0; j <= N; ++j) { ez_prev[j] = 0.0; bk[j] = 0.0; }
+    direct_t c = {&g, &s, np, n4, x, y, px, py, d0, w, nion, NULL, NULL, ez_prev, ez_k, jz_k,
+                  f0, f1, ys, yn, dez, bstar, 0, 0};
+    int64_t clamps = 0, walls = 0;
+
+    for (int k = 0; k < p->n_xi; ++k) {
+        c.jb_k = jb + (int64_t)k * N1;
+        c.jb_n = jb + (int64_t)(k + 1 < p->n_xi ? k + 1 : k) * N1;
+        c.last = k + 1 >= p->n_xi;
+        /* the B-independent fields of slice k */
+        eval_core_b(&g, &s, np, x, y, px, py, d0, w, nion, c.jb_k, NULL, NULL, NULL, NULL, &c.scratch_clamps, bk);
+        for (int j = 0; j <= N; ++j) {
+            ez_k[j] = s.Ez[j];
+            jz_k[j] = s.Jz[j];
+            psi_k[j] = s.psi[j];
+            fields[3 * plane + (int64_t)k * N1 + j] = -s.dpsi[j];
+        }
+        int it = 0;
+        for (;;) {
+            direct_phi(&c, bk, phi);
+            double rmax = 0.0, bmax = 0.0;
+            for (int j = 0; j <= N; ++j) {
+                res[j] = phi[j] - bk[j];
+                rmax = fmax(rmax, fabs(res[j]));
+                bmax = fmax(bmax, fabs(phi[j]));
+            }
+            if (rmax <= tol * bmax || it >= iters) break;
+            ++it;
+            direct_gmres(&c, bk, phi, res, dx, N1, V, H, work, tmp);
+            for (int j = 0; j <= N; ++j) bk[j] += dx[j];
+        }
+        if (iterations) iterations[k] = it;
+        for (int j = 0; j <= N; ++j) {
+            fields[(int64_t)k * N1 + j] = psi_k[j];
+            fields[plane + (int64_t)k * N1 + j] = ez_k[j];
+            fields[2 * plane + (int64_t)k * N1 + j] = bk[j];
+        }
+        if (k == p->n_xi - 1) break;
+        /* accept the step with the converged B_k (its clamps count) */
+        c.scratch_clamps = 0;
+        direct_phi(&c, bk, phi);
+        clamps += c.scratch_clamps;
+        for (int64_t i = 0; i < np; ++i) {
+            x[i] = yn[i];
+            y[i] = yn[n4 + i];
+            px[i] = yn[2 * n4 + i];
+            py[i] = yn[3 * n4 + i];
+        }
+        walls += reflect_wall(&g, np, x, y, px, py);
+        for (int j = 0; j <= N; ++j) ez_prev[j] = ez_k[j];
+    }
+    if (counters) {
+        counters[0] = clamps;
+        counters[1] = walls;
+        counters[2] = count_nonfinite(fields, 4 * plane);
+    }
+    free(f0); free(f1); free(ys); free(yn); free(rows); free(V); free(H);
+    scratch_free(&s);
+    grid_free(&g);
+    return 0;
 }
 
 /*

@@ -100,6 +100,18 @@ int or_march_traj(const or_problem* p, int64_t np,
                   const double* jb, double* fields, int64_t* counters,
                   int32_t stride, double* traj);
 
+/* The plasma response with B_theta from Eq. (6) directly,
+ * (1/r) d_r (r B) = d_xi E_z + J_z, with d_xi E_z = d^2 psi / d xi^2 taken
+ * implicitly, (E_z,k+1 - E_z,k) / dxi, and solved per slice by Newton steps
+ * (GMRES for each; at most iters steps, until the residual is at most tol of
+ * max |B|).  First order in dxi.  Same outputs as or_march (no diag);
+ * iterations (n_xi entries, may be NULL) receives the Newton steps used. */
+int or_march_direct(const or_problem* p, int64_t np,
+                    double* x, double* y, double* px, double* py,
+                    const double* d0, const double* w, const double* nion,
+                    const double* jb, double* fields, int64_t* counters,
+                    int32_t iters, double tol, int32_t* iterations);
+
 /* Beam advance in time with frozen fields, Eqs. (8)-(11), Boris rotation.
  * n_out counts particle-steps that sampled no field (outside the window). */
 int or_beam_push(const or_problem* p, int64_t n_beam,

@@ -260,6 +260,34 @@ def test_p5_eq6_btheta(O):
     assert errs[0] < 5e-3 and errs[0] / errs[1] > 3.5, errs      # second order off the axis
 
 
+def test_next3_direct_eq6_converges_to_closed_form_and_helmholtz(O):
+    """B_theta from Eq. (6) as written, (1/r) d_r (r B) = d_xi E_z + J_z, with
+    the implicit d_xi E_z and a Newton-GMRES solve per slice: on the weak
+    bunch its fields converge at first order in the grid (halving dr and
+    dxi together) to the linear closed form, and to the Helmholtz-form march
+    (reading R4), off the axis; Newton converges in a few steps."""
+    from tests import linear_theory
+    d_cf, d_r4 = [], []
+    for (nr, nxi) in ((32, 128), (64, 256), (128, 512)):
+        p = inputs.weak_single_bunch(n_b0=1e-4, n_r=nr, n_xi=nxi)
+        cf = linear_theory.fields(p)
+        st = O.load_plasma(p, None)
+        jb = O.beam_current_analytic(p)
+        f4, _, _ = O.march(p, {k: v.copy() for k, v in st.items()}, jb)
+        fd, c, its = O.march_direct(p, {k: v.copy() for k, v in st.items()}, jb)
+        assert c[2] == 0 and its.max() <= 8
+        j0 = int(round(0.2 / (p.r_max / p.n_r)))
+
+        def off(a, b, i):
+            return np.max(np.abs(a[i][:, j0:] - b[i][:, j0:])) / np.max(np.abs(b[i]))
+        d_cf.append([off(fd, cf, i) for i in range(4)])
+        d_r4.append([off(fd, f4, i) for i in range(4)])
+    d_cf, d_r4 = np.array(d_cf), np.array(d_r4)
+    assert np.all(d_cf[-1] < 2e-2) and np.all(d_r4[-1] < 2e-2), (d_cf, d_r4)
+    assert np.all(d_cf[1] / d_cf[2] > 1.7) and np.all(d_r4[1] / d_r4[2] > 1.7), (d_cf, d_r4)
+    assert np.all(d_cf[0] / d_cf[1] > 1.7), d_cf
+
+
 # ---------------------------------------------------------------------------
 # P6: static-field invariant
 # ---------------------------------------------------------------------------
