@@ -275,15 +275,16 @@ def scan_cpu_baseline(probs, n_slices: int):
                       f"time; loading outside the timed marches)"}
 
 
-def grad_bench(args):
+def grad_bench(args, prec: str = "fp64"):
     """Gradient of the witness gain on the 256 x 2048, 16 ppc, 2e5-particle,
-    20-step workload (blowout driver n_d = 8, u_th = 0.02, FP64, checkpoints
-    every 64 slices): time of the plain forward (beam load + current +
-    response + 20 pushes + gain), of the recording forward and of the reverse
-    pass, each the best of a few runs timed with HIP events."""
+    20-step workload (blowout driver n_d = 8, u_th = 0.02, checkpoints every
+    64 slices), in FP64 or mixed precision (float recorded march and float
+    per-particle adjoint arithmetic): time of the plain forward (beam load +
+    current + response + 20 pushes + gain), of the recording forward and of
+    the reverse pass, each the best of a few runs timed with HIP events."""
     import torch
     from paper_1411_3246_amd import inputs, wake
-    p = inputs.gradient_case()
+    p = inputs.gradient_case().replace(prec=prec)
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
@@ -321,7 +322,7 @@ def grad_bench(args):
     torch.cuda.empty_cache()
     return {
         "workload": p.name, "n_d": p.bunches[0].n_peak, "u_th": p.u_th, "n_steps": p.n_steps,
-        "checkpoint_every": 64, "precision": "fp64",
+        "checkpoint_every": 64, "precision": prec,
         "forward_ms": fwd, "recording_forward_ms": rec, "backward_ms": bwd,
         "adjoint_over_forward": bwd / fwd, "gradient_over_forward": (rec + bwd) / fwd,
         "objective": g, "objective_plain": g_plain,
@@ -647,9 +648,12 @@ def main():
         line["batched_speedup"] = sc["batched_speedup"]
         line["batched_updates_per_s"] = sc["batched_updates_per_s"]
     if not args.no_grad:
-        gr = grad_bench(args)
+        gr = grad_bench(args, "fp64")
+        gm = grad_bench(args, "mixed")
         line["gradient"] = gr
-        line["adjoint_over_forward"] = gr["adjoint_over_forward"]
+        line["gradient_mixed"] = gm
+        line["adjoint_over_forward"] = gm["adjoint_over_forward"]
+        line["adjoint_over_forward_fp64"] = gr["adjoint_over_forward"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -345,8 +345,11 @@ wk_status wk_gain_histogram(const wk_plan* plan, const wk_beam_bufs* beam, int32
 wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
                      double* d_out, void* stream);
 
-/* Gradient of the witness energy gain (reverse mode, FP64 plans with a
- * two-bunch macroparticle beam).  The objective G is the charge-weighted mean
+/* Gradient of the witness energy gain (reverse mode, FP64 or WK_MIXED plans
+ * with a two-bunch macroparticle beam; in a mixed plan the recorded march
+ * and the per-particle arithmetic of the reverse pass are float, as in
+ * wk_plasma_response, while the recorded rows, particle states, adjoint
+ * accumulators and the solves stay double).  The objective G is the charge-weighted mean
  * gamma gain of the witness after one plasma response to the loaded beam and
  * n_steps beam advances by dt in that response's frozen fields (Section II A:
  * plasma response for the frozen beam, then the beam advanced over the long

@@ -51,7 +51,7 @@ struct RecordHooks : M::NoRecord {
         if (k % every != 0) return;
         const int64_t np = m.d.np;
         double* c = ckpt + (int64_t)(k / every) * 4 * np;
-        m.for_idx([&](int64_t i, const dev::Part<double>& p) {
+        m.for_idx([&](int64_t i, const auto& p) {
             c[i] = p.x;
             c[np + i] = p.y;
             c[2 * np + i] = p.px;
@@ -87,11 +87,11 @@ struct RecordHooks : M::NoRecord {
 
 constexpr int kRecK = 8;
 
-template <int GEOM, bool WARM, int T, bool RES>
+template <typename R, int GEOM, bool WARM, int T, bool RES>
 __global__ __launch_bounds__(T) void k_march_record(MarchDesc d, double* tape, double* ckpt, int every)
 {
     extern __shared__ double smem[];
-    using M = dev::Marcher<double, GEOM, WARM, T, kRecK, RES, false>;
+    using M = dev::Marcher<R, GEOM, WARM, T, kRecK, RES, false>;
     M m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
     RecordHooks<M> hooks(tape, ckpt, every);
     m.run(hooks);
@@ -127,7 +127,10 @@ enum AdjRow {
 };
 constexpr int kSetRows = 7;   // per stage: psi, psi', E_z, B, M1, M2, M4
 
-template <int GEOM, bool WARM, int kAdjT>
+// P: the type of the per-particle arithmetic of the vector-Jacobian
+// products (double, or float for mixed plans, as in their forward march);
+// states, rows and adjoint accumulators stay double.
+template <int GEOM, bool WARM, int kAdjT, typename P>
 struct Reverse {
     const AdjDesc& a;
     double* sm;
@@ -257,7 +260,7 @@ struct Reverse {
                 if (k == k1) break;
                 const double* t0 = tape_rows(a.tape, k, 0, N1);
                 const double* t1 = tape_rows(a.tape, k, 1, N1);
-                const adj::Der g0 = adj::derivative<GEOM, WARM>(y, d0, t0 + TP_PSI * N1, t0 + TP_DPSI * N1,
+                const adj::Der g0 = adj::derivative<GEOM, WARM, P>(y, d0, t0 + TP_PSI * N1, t0 + TP_DPSI * N1,
                                                                 t0 + TP_B * N1, G);
                 adj::St yst = y;
                 yst.x = y.x + dxi * g0.fx;
@@ -266,7 +269,7 @@ struct Reverse {
                     yst.y = y.y + dxi * g0.fy;
                     yst.py = y.py + dxi * g0.fpy;
                 }
-                const adj::Der g1 = adj::derivative<GEOM, WARM>(yst, d0, t1 + TP_PSI * N1, t1 + TP_DPSI * N1,
+                const adj::Der g1 = adj::derivative<GEOM, WARM, P>(yst, d0, t1 + TP_PSI * N1, t1 + TP_DPSI * N1,
                                                                 t1 + TP_B * N1, G);
                 y.x = y.x + hd * (g0.fx + g1.fx);
                 y.px = y.px + hd * (g0.fpx + g1.fpx);
@@ -403,7 +406,7 @@ struct Reverse {
         // E_z = -int_r^{r_max} J_r (trapezoid): J_r adjoint from prefix sums
         // (a block-wide scan)
         {
-            double* P = row(A_LAM);
+            double* pre = row(A_LAM);
             const double* ezb = row(A_EZ);
             int j0, j1;
             owned(N, j0, j1);
@@ -413,12 +416,12 @@ struct Reverse {
             double run = block_excl(s, dev::scan_scratch(), tot);
             for (int j = j0; j < j1; ++j) {
                 run += ezb[j];
-                P[j] = run;
+                pre[j] = run;
             }
             __syncthreads();
             for (int m = tid; m < N1; m += kAdjT) {
-                const double pm = m <= N - 1 ? P[m] : 0.0;
-                const double pm1 = m >= 1 ? P[m - 1] : 0.0;
+                const double pm = m <= N - 1 ? pre[m] : 0.0;
+                const double pm1 = m >= 1 ? pre[m - 1] : 0.0;
                 row(A_G0)[m] = -(0.5 * h) * (pm + pm1) * inv_volume(m);
             }
         }
@@ -486,7 +489,7 @@ struct Reverse {
             if (pidx(m) >= a.np) continue;
             const int64_t s = slot(m);
             const adj::St y = get(stt, s);
-            const adj::Geo g = adj::geo_of<GEOM, WARM>(y, G);
+            const adj::GeoT<P> g = adj::geo_of<GEOM, WARM, P>(y, G);
             double gr[7], dr[7];
 #pragma unroll
             for (int r = 0; r < 7; ++r) {
@@ -498,7 +501,7 @@ struct Reverse {
             adj::St sb = get(acc, s);
             double d0bar = d0b[s], wbar = wb[s];
             const adj::DerAdj o =
-                adj::moment_terms_vjp<GEOM, WARM>(y, d0t[s], wt[s], psi, G, gr, dr, sb, d0bar, wbar);
+                adj::moment_terms_vjp<GEOM, WARM, P>(y, d0t[s], wt[s], psi, G, gr, dr, sb, d0bar, wbar);
             deposit(A_PSI, o.j, o.t, o.gpsi);
             put(acc, s, sb);
             d0b[s] = d0bar;
@@ -515,7 +518,7 @@ struct Reverse {
             const adj::St y = get(stt, s);
             adj::St sb = get(acc, s);
             double wbar = wb[s];
-            adj::s_term_vjp<GEOM, WARM>(y, wt[s], G, row(A_S), sb, wbar);
+            adj::s_term_vjp<GEOM, WARM, P>(y, wt[s], G, row(A_S), sb, wbar);
             put(acc, s, sb);
             wb[s] = wbar;
         }
@@ -558,7 +561,7 @@ struct Reverse {
                         const adj::St y = get(yk, s);
                         const double d0 = d0t[s];
                         const adj::Der g0 =
-                            adj::derivative<GEOM, WARM>(y, d0, row(K_PSI), row(K_DPSI), row(K_B), G);
+                            adj::derivative<GEOM, WARM, P>(y, d0, row(K_PSI), row(K_DPSI), row(K_B), G);
                         adj::St yst = y;
                         yst.x = y.x + dxi * g0.fx;
                         yst.px = y.px + dxi * g0.fpx;
@@ -567,7 +570,7 @@ struct Reverse {
                             yst.py = y.py + dxi * g0.fpy;
                         }
                         const adj::Der g1 =
-                            adj::derivative<GEOM, WARM>(yst, d0, row(S_PSI), row(S_DPSI), row(S_B), G);
+                            adj::derivative<GEOM, WARM, P>(yst, d0, row(S_PSI), row(S_DPSI), row(S_B), G);
                         adj::St yt = y;
                         yt.x = y.x + hd * (g0.fx + g1.fx);
                         yt.px = y.px + hd * (g0.fpx + g1.fpx);
@@ -582,7 +585,7 @@ struct Reverse {
                         const adj::Der fb{hd * b.x, hd * b.y, hd * b.px, hd * b.py};
                         adj::St sb{0.0, 0.0, 0.0, 0.0};
                         double d0bar = d0b[s];
-                        const adj::DerAdj o = adj::derivative_vjp<GEOM, WARM>(yst, d0, row(S_PSI), row(S_DPSI),
+                        const adj::DerAdj o = adj::derivative_vjp<GEOM, WARM, P>(yst, d0, row(S_PSI), row(S_DPSI),
                                                                               row(S_B), G, fb, sb, d0bar);
                         deposit(A_PSI, o.j, o.t, o.gpsi);
                         deposit(A_DPSI, o.j, o.t, o.gdpsi);
@@ -608,7 +611,7 @@ struct Reverse {
                         const adj::St yst = get(ys, s);
                         adj::St sb = get(ysb, s);
                         double wbar = wb[s];
-                        adj::s_term_vjp<GEOM, WARM>(yst, wt[s], G, row(A_S), sb, wbar);
+                        adj::s_term_vjp<GEOM, WARM, P>(yst, wt[s], G, row(A_S), sb, wbar);
                         wb[s] = wbar;
                         adj::St b = get(yb, s);
                         b.x += sb.x;
@@ -620,7 +623,7 @@ struct Reverse {
                                           f0.py + dxi * sb.py};
                         const adj::St y = get(yk, s);
                         double d0bar = d0b[s];
-                        const adj::DerAdj o = adj::derivative_vjp<GEOM, WARM>(y, d0t[s], row(K_PSI), row(K_DPSI),
+                        const adj::DerAdj o = adj::derivative_vjp<GEOM, WARM, P>(y, d0t[s], row(K_PSI), row(K_DPSI),
                                                                               row(K_B), G, fb, b, d0bar);
                         deposit(A_PSI, o.j, o.t, o.gpsi);
                         deposit(A_DPSI, o.j, o.t, o.gdpsi);
@@ -654,11 +657,11 @@ struct Reverse {
     }
 };
 
-template <int GEOM, bool WARM, int T>
+template <int GEOM, bool WARM, int T, typename P>
 __global__ __launch_bounds__(T) void k_adjoint_march(AdjDesc a)
 {
     extern __shared__ double smem[];
-    Reverse<GEOM, WARM, T> r(a, smem);
+    Reverse<GEOM, WARM, T, P> r(a, smem);
     r.run();
 }
 
@@ -673,7 +676,8 @@ struct BeamGeom {
 };
 
 // history: [n_steps + 1][6][n] (x, y, xi, px, py, pz)
-__global__ __launch_bounds__(kBlk) void k_push_record(BeamGeom g, int64_t n, wk_beam_bufs b, const double* fields,
+template <typename FT>
+__global__ __launch_bounds__(kBlk) void k_push_record(BeamGeom g, int64_t n, wk_beam_bufs b, const FT* fields,
                                                       int n_steps, double dt, double* hist,
                                                       unsigned long long* counters)
 {
@@ -691,7 +695,7 @@ __global__ __launch_bounds__(kBlk) void k_push_record(BeamGeom g, int64_t n, wk_
         H[4 * n + i] = py;
         H[5 * n + i] = pz;
         if (s == n_steps) break;
-        const adj::BeamCell c = adj::boris_step<double>(g.geom, g.n_r, g.n_xi, g.r_max, g.h, g.xi_min, g.dxi,
+        const adj::BeamCell c = adj::boris_step<double, FT>(g.geom, g.n_r, g.n_xi, g.r_max, g.h, g.xi_min, g.dxi,
                                                         fields + plane, fields + 2 * plane, fields + 3 * plane, x,
                                                         y, xi, px, py, pz, dt, false);
         out += c.inside ? 0 : 1;
@@ -726,7 +730,8 @@ __global__ __launch_bounds__(1024) void k_witness_weight(int64_t n, wk_beam_bufs
 // the adjoint of the gathered fields goes to fbar ([4][n_xi][N1], planes
 // E_z, B, W) with the bilinear weights.  sb0: [6][n] adjoint of the state
 // before the push.
-__global__ __launch_bounds__(kBlk) void k_push_adjoint(BeamGeom g, int64_t n, wk_beam_bufs b, const double* fields,
+template <typename FT>
+__global__ __launch_bounds__(kBlk) void k_push_adjoint(BeamGeom g, int64_t n, wk_beam_bufs b, const FT* fields,
                                                        int n_steps, double dt, const double* hist,
                                                        const double* wsum, double* fbar, double* sb0)
 {
@@ -752,7 +757,7 @@ __global__ __launch_bounds__(kBlk) void k_push_adjoint(BeamGeom g, int64_t n, wk
             v[q].d[q] = 1.0;
         }
         const adj::BeamCell c =
-            adj::boris_step<adj::Dual>(g.geom, g.n_r, g.n_xi, g.r_max, g.h, g.xi_min, g.dxi, fields + plane,
+            adj::boris_step<adj::Dual, FT>(g.geom, g.n_r, g.n_xi, g.r_max, g.h, g.xi_min, g.dxi, fields + plane,
                                        fields + 2 * plane, fields + 3 * plane, v[0], v[1], v[2], v[3], v[4], v[5],
                                        dt, true);
         double nb[6], fb[3];
@@ -929,7 +934,7 @@ __global__ void k_zero_f64(double* p, int64_t n)
 
 int64_t blocks_for(int64_t n, int b) { return (n + b - 1) / b; }
 
-template <int GEOM, bool WARM>
+template <typename R, int GEOM, bool WARM>
 hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double* ckpt, int every, hipStream_t s)
 {
     const size_t lds = march_lds_bytes(d.n_r + 1, threads);
@@ -943,36 +948,53 @@ hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double
     const bool res = d.np <= (int64_t)threads * kRecK && lds + extra <= 159 * 1024;
     switch (threads) {
     case 256:
-        return res ? go(k_march_record<GEOM, WARM, 256, true>, lds + extra) : go(k_march_record<GEOM, WARM, 256, false>, lds);
+        return res ? go(k_march_record<R, GEOM, WARM, 256, true>, lds + extra)
+                   : go(k_march_record<R, GEOM, WARM, 256, false>, lds);
     case 512:
-        return res ? go(k_march_record<GEOM, WARM, 512, true>, lds + extra) : go(k_march_record<GEOM, WARM, 512, false>, lds);
+        return res ? go(k_march_record<R, GEOM, WARM, 512, true>, lds + extra)
+                   : go(k_march_record<R, GEOM, WARM, 512, false>, lds);
     case 1024:
-        return res ? go(k_march_record<GEOM, WARM, 1024, true>, lds + extra)
-                   : go(k_march_record<GEOM, WARM, 1024, false>, lds);
+        return res ? go(k_march_record<R, GEOM, WARM, 1024, true>, lds + extra)
+                   : go(k_march_record<R, GEOM, WARM, 1024, false>, lds);
     default:
         return hipErrorInvalidValue;
     }
 }
 
-template <int GEOM, bool WARM, int T>
+template <int GEOM, bool WARM, int T, typename P>
 hipError_t launch_reverse_tt(const AdjDesc& a, hipStream_t s)
 {
     const size_t lds = (size_t)NUM_ADJ_ROWS * lds_stride(a.n_r + 1) * sizeof(double);
-    auto kern = k_adjoint_march<GEOM, WARM, T>;
+    auto kern = k_adjoint_march<GEOM, WARM, T, P>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(1), dim3(T), lds, s, a);
     return hipGetLastError();
 }
 
-template <int GEOM, bool WARM>
+template <int GEOM, bool WARM, typename P>
 hipError_t launch_reverse_t(const AdjDesc& a, int threads, hipStream_t s)
 {
     switch (threads) {
-    case 256: return launch_reverse_tt<GEOM, WARM, 256>(a, s);
-    case 512: return launch_reverse_tt<GEOM, WARM, 512>(a, s);
-    default: return launch_reverse_tt<GEOM, WARM, 1024>(a, s);
+    case 256: return launch_reverse_tt<GEOM, WARM, 256, P>(a, s);
+    case 512: return launch_reverse_tt<GEOM, WARM, 512, P>(a, s);
+    default: return launch_reverse_tt<GEOM, WARM, 1024, P>(a, s);
     }
+}
+
+template <typename P>
+hipError_t launch_reverse_p(const AdjDesc& a, int geom, bool warm, int threads, hipStream_t s)
+{
+    if (geom == WK_CYL)
+        return warm ? launch_reverse_t<WK_CYL, true, P>(a, threads, s) : launch_reverse_t<WK_CYL, false, P>(a, threads, s);
+    return warm ? launch_reverse_t<WK_SLAB, true, P>(a, threads, s) : launch_reverse_t<WK_SLAB, false, P>(a, threads, s);
+}
+
+// Plasma constants of a mixed plan (float) as double for the reverse pass.
+__global__ void k_to_f64(const float* in, double* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
 }
 
 }  // namespace
@@ -986,13 +1008,21 @@ size_t adjoint_scratch_doubles(int64_t np, int every, int threads)
     return (size_t)((int64_t)every * 4 * slots + 16 * slots + 4 * slots);
 }
 
-hipError_t launch_march_record(const MarchDesc& d, int threads, double* tape, double* ckpt, int every, hipStream_t s)
+template <typename R>
+hipError_t launch_record_r(const MarchDesc& d, int threads, double* tape, double* ckpt, int every, hipStream_t s)
 {
     if (d.geom == WK_CYL)
-        return d.warm ? launch_record_t<WK_CYL, true>(d, threads, tape, ckpt, every, s)
-                      : launch_record_t<WK_CYL, false>(d, threads, tape, ckpt, every, s);
-    return d.warm ? launch_record_t<WK_SLAB, true>(d, threads, tape, ckpt, every, s)
-                  : launch_record_t<WK_SLAB, false>(d, threads, tape, ckpt, every, s);
+        return d.warm ? launch_record_t<R, WK_CYL, true>(d, threads, tape, ckpt, every, s)
+                      : launch_record_t<R, WK_CYL, false>(d, threads, tape, ckpt, every, s);
+    return d.warm ? launch_record_t<R, WK_SLAB, true>(d, threads, tape, ckpt, every, s)
+                  : launch_record_t<R, WK_SLAB, false>(d, threads, tape, ckpt, every, s);
+}
+
+hipError_t launch_march_record(const MarchDesc& d, int prec, int threads, double* tape, double* ckpt, int every,
+                               hipStream_t s)
+{
+    return prec == WK_FP64 ? launch_record_r<double>(d, threads, tape, ckpt, every, s)
+                           : launch_record_r<float>(d, threads, tape, ckpt, every, s);
 }
 
 hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
@@ -1004,8 +1034,23 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     const int64_t nb = gd.n_beam;
     hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(4 * plane, kBlk)), dim3(kBlk), 0, s, gd.fbar, 4 * plane);
     hipLaunchKernelGGL(k_witness_weight, dim3(1), dim3(1024), 0, s, nb, gd.beam, gd.wsum);
-    hipLaunchKernelGGL(k_push_adjoint, dim3(blocks_for(nb, kBlk)), dim3(kBlk), 0, s, bg, nb, gd.beam, gd.fields,
-                       gd.n_steps, gd.dt, gd.hist, gd.wsum, gd.fbar, gd.sb0);
+    if (gd.prec == WK_FP64)
+        hipLaunchKernelGGL(k_push_adjoint<double>, dim3(blocks_for(nb, kBlk)), dim3(kBlk), 0, s, bg, nb, gd.beam,
+                           (const double*)gd.fields, gd.n_steps, gd.dt, gd.hist, gd.wsum, gd.fbar, gd.sb0);
+    else
+        hipLaunchKernelGGL(k_push_adjoint<float>, dim3(blocks_for(nb, kBlk)), dim3(kBlk), 0, s, bg, nb, gd.beam,
+                           (const float*)gd.fields, gd.n_steps, gd.dt, gd.hist, gd.wsum, gd.fbar, gd.sb0);
+    const double* pd0 = (const double*)gd.march.d0;
+    const double* pw = (const double*)gd.march.w;
+    if (gd.prec != WK_FP64) {
+        const int64_t np = gd.march.np;
+        hipLaunchKernelGGL(k_to_f64, dim3(blocks_for(np, kBlk)), dim3(kBlk), 0, s, (const float*)gd.march.d0,
+                           gd.d0_f64, np);
+        hipLaunchKernelGGL(k_to_f64, dim3(blocks_for(np, kBlk)), dim3(kBlk), 0, s, (const float*)gd.march.w,
+                           gd.w_f64, np);
+        pd0 = gd.d0_f64;
+        pw = gd.w_f64;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     AdjDesc a;
@@ -1018,8 +1063,8 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     a.h = gd.grid.h;
     a.dxi = gd.grid.dxi;
     a.d_min = gd.march.d_min;
-    a.d0 = (const double*)gd.march.d0;
-    a.w = (const double*)gd.march.w;
+    a.d0 = pd0;
+    a.w = pw;
     a.tape = gd.tape;
     a.ckpt = gd.ckpt;
     a.fbar = gd.fbar;
@@ -1028,12 +1073,8 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     a.ybar_out = gd.ybar;
     a.d0bar_out = gd.d0bar;
     a.wbar_out = gd.wbar;
-    if (gd.grid.geom == WK_CYL)
-        e = gd.march.warm ? launch_reverse_t<WK_CYL, true>(a, gd.threads, s)
-                          : launch_reverse_t<WK_CYL, false>(a, gd.threads, s);
-    else
-        e = gd.march.warm ? launch_reverse_t<WK_SLAB, true>(a, gd.threads, s)
-                          : launch_reverse_t<WK_SLAB, false>(a, gd.threads, s);
+    e = gd.prec == WK_FP64 ? launch_reverse_p<double>(a, gd.grid.geom, gd.march.warm != 0, gd.threads, s)
+                           : launch_reverse_p<float>(a, gd.grid.geom, gd.march.warm != 0, gd.threads, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_current_adjoint, dim3(blocks_for(nb, kBlk)), dim3(kBlk), 0, s, bg, nb, gd.beam, gd.hist,
                        gd.jbbar, gd.sb0, gd.wbar_beam);
@@ -1054,20 +1095,24 @@ hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s)
     t.ybar = gd.ybar;
     t.d0bar = gd.d0bar;
     t.wbar = gd.wbar;
-    t.pw = (const double*)gd.march.w;
-    t.pd0 = (const double*)gd.march.d0;
+    t.pw = pw;
+    t.pd0 = pd0;
     hipLaunchKernelGGL(k_theta_partial, dim3(kThetaBlocks), dim3(kBlk), 0, s, t, gd.partials);
     hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(64), 0, s, gd.partials, kThetaBlocks, gd.gbar, gd.grad);
     return hipGetLastError();
 }
 
-hipError_t launch_push_record(const GridDesc& g, int64_t n, const wk_beam_bufs& b, const double* fields,
+hipError_t launch_push_record(const GridDesc& g, int64_t n, const wk_beam_bufs& b, const void* fields, int prec,
                               int n_steps, double dt, double* hist, unsigned long long* counters, hipStream_t s)
 {
     const BeamGeom bg{g.geom, g.n_r, g.n_xi, g.r_max, g.h, g.xi_min, g.dxi};
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_push_record, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, s, bg, n, b, fields, n_steps, dt,
-                       hist, counters);
+    if (prec == WK_FP64)
+        hipLaunchKernelGGL(k_push_record<double>, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, s, bg, n, b,
+                           (const double*)fields, n_steps, dt, hist, counters);
+    else
+        hipLaunchKernelGGL(k_push_record<float>, dim3(blocks_for(n, kBlk)), dim3(kBlk), 0, s, bg, n, b,
+                           (const float*)fields, n_steps, dt, hist, counters);
     return hipGetLastError();
 }
 

@@ -26,67 +26,70 @@ struct St {
 
 // Hat geometry of a particle (as in the march: the radius is |(x, y)| for a
 // warm cylindrical plasma and |x| otherwise, folded at the wall).
-struct Geo {
-    double r, rho, sw, sg, t;
+template <typename P = double>
+struct GeoT {
+    P r, rho, sw, sg, t;
     int j;
     bool rho_clamped;
 };
+using Geo = GeoT<double>;
 
-template <int GEOM, bool WARM>
-__host__ __device__ inline Geo geo_of(const St& s, const Grid& G)
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline GeoT<P> geo_of(const St& s, const Grid& G)
 {
-    Geo g;
-    const double r = (GEOM == WK_CYL && WARM) ? sqrt(s.x * s.x + s.y * s.y) : fabs(s.x);
+    GeoT<P> g;
+    const P r = (GEOM == WK_CYL && WARM) ? sqrt(s.x * s.x + s.y * s.y) : fabs(s.x);
     g.r = r;
-    double rho = r, sw = 1.0;
+    P rho = r, sw = P(1.0);
     g.rho_clamped = false;
     if (r > G.rmax) {
-        sw = -1.0;
-        rho = 2.0 * G.rmax - r;
-        if (rho < 0.0) {
-            rho = 0.0;
+        sw = -P(1.0);
+        rho = P(2.0) * G.rmax - r;
+        if (rho < P(0.0)) {
+            rho = P(0.0);
             g.rho_clamped = true;
         }
     }
     g.rho = rho;
     g.sw = sw;
-    g.sg = (GEOM == WK_SLAB) ? ((s.x < 0.0) ? -sw : sw) : sw;
-    const double u = rho / G.h;
+    g.sg = (GEOM == WK_SLAB) ? ((s.x < P(0.0)) ? -sw : sw) : sw;
+    const P u = rho / G.h;
     int j = (int)floor(u);
     j = j < 0 ? 0 : (j > G.N - 1 ? G.N - 1 : j);
     g.j = j;
-    g.t = u - (double)j;
+    g.t = u - (P)j;
     return g;
 }
 
 // Adjoint of the radius: add r_bar d r / d(x, y) to (xb, yb).
-template <int GEOM, bool WARM>
-__host__ __device__ inline void radius_vjp(const St& s, const Geo& g, double rb, double& xb, double& yb)
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline void radius_vjp(const St& s, const GeoT<P>& g, P rb, double& xb, double& yb)
 {
     if (GEOM == WK_CYL && WARM) {
-        if (g.r > 0.0) {
+        if (g.r > P(0.0)) {
             xb += rb * s.x / g.r;
             yb += rb * s.y / g.r;
         }
     } else {
-        xb += rb * (s.x < 0.0 ? -1.0 : (s.x > 0.0 ? 1.0 : 0.0));
+        xb += rb * (s.x < P(0.0) ? -P(1.0) : (s.x > P(0.0) ? P(1.0) : P(0.0)));
     }
 }
 
 // Adjoint of the hat coordinate t = rho / h - j (and of a direct dependence
 // on the folded radius rho_b and the unfolded radius r_b).
-template <int GEOM, bool WARM>
-__host__ __device__ inline void geo_vjp(const St& s, const Geo& g, const Grid& G, double tb, double rhob,
-                                        double rb, double& xb, double& yb)
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline void geo_vjp(const St& s, const GeoT<P>& g, const Grid& G, P tb, P rhob,
+                                        P rb, double& xb, double& yb)
 {
-    const double rho_bar = tb / G.h + rhob;
+    const P rho_bar = tb / G.h + rhob;
     if (!g.rho_clamped) rb += g.sw * rho_bar;
-    radius_vjp<GEOM, WARM>(s, g, rb, xb, yb);
+    radius_vjp<GEOM, WARM, P>(s, g, rb, xb, yb);
 }
 
-__host__ __device__ inline double hat_gather(const double* row, const Geo& g)
+template <typename P = double>
+__host__ __device__ inline P hat_gather(const double* row, const GeoT<P>& g)
 {
-    return (1.0 - g.t) * row[g.j] + g.t * row[g.j + 1];
+    return (P(1.0) - g.t) * (P)row[g.j] + g.t * (P)row[g.j + 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -96,35 +99,35 @@ struct Der {
     double fx, fy, fpx, fpy;
 };
 
-template <int GEOM, bool WARM>
-__host__ __device__ inline Der derivative(const St& s, double d0, const double* psi, const double* dpsi,
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline Der derivative(const St& s, P d0, const double* psi, const double* dpsi,
                                           const double* bt, const Grid& G)
 {
-    const Geo g = geo_of<GEOM, WARM>(s, G);
-    double D = d0 + hat_gather(psi, g);
+    const GeoT<P> g = geo_of<GEOM, WARM, P>(s, G);
+    P D = d0 + hat_gather<P>(psi, g);
     if (D < G.dmin) D = G.dmin;
-    const double px = s.px;
-    const double py = WARM ? s.py : 0.0;
-    const double p2 = px * px + py * py;
-    const double iD = 1.0 / D;
-    const double gam = (1.0 + p2 + D * D) * (0.5 * iD);
-    const double F = (gam * iD) * hat_gather(dpsi, g) - hat_gather(bt, g);
+    const P px = s.px;
+    const P py = WARM ? s.py : P(0.0);
+    const P p2 = px * px + py * py;
+    const P iD = P(1.0) / D;
+    const P gam = (P(1.0) + p2 + D * D) * (P(0.5) * iD);
+    const P F = (gam * iD) * hat_gather<P>(dpsi, g) - hat_gather<P>(bt, g);
     Der f;
     f.fx = px * iD;
     if (GEOM == WK_CYL) {
-        f.fy = WARM ? py * iD : 0.0;
-        if (g.r > 0.0) {
-            const double fr = g.sw * F * (1.0 / g.r);
+        f.fy = WARM ? py * iD : P(0.0);
+        if (g.r > P(0.0)) {
+            const P fr = g.sw * F * (P(1.0) / g.r);
             f.fpx = fr * s.x;
-            f.fpy = WARM ? fr * s.y : 0.0;
+            f.fpy = WARM ? fr * s.y : P(0.0);
         } else {
-            f.fpx = 0.0;
-            f.fpy = 0.0;
+            f.fpx = P(0.0);
+            f.fpy = P(0.0);
         }
     } else {
-        f.fy = 0.0;
+        f.fy = P(0.0);
         f.fpx = g.sg * F;
-        f.fpy = 0.0;
+        f.fpy = P(0.0);
     }
     return f;
 }
@@ -137,33 +140,34 @@ struct DerAdj {
     int j;
 };
 
-template <int GEOM, bool WARM>
-__host__ __device__ inline DerAdj derivative_vjp(const St& s, double d0, const double* psi, const double* dpsi,
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline DerAdj derivative_vjp(const St& s, P d0, const double* psi, const double* dpsi,
                                                  const double* bt, const Grid& G, const Der& fb, St& sb,
                                                  double& d0b)
 {
-    const Geo g = geo_of<GEOM, WARM>(s, G);
-    const double ps0 = psi[g.j], ps1 = psi[g.j + 1];
-    const double dp0 = dpsi[g.j], dp1 = dpsi[g.j + 1];
-    const double b0 = bt[g.j], b1 = bt[g.j + 1];
-    const double psig = (1.0 - g.t) * ps0 + g.t * ps1;
-    const double dpg = (1.0 - g.t) * dp0 + g.t * dp1;
-    const double bg = (1.0 - g.t) * b0 + g.t * b1;
-    double D = d0 + psig;
+    const GeoT<P> g = geo_of<GEOM, WARM, P>(s, G);
+    const P ps0 = psi[g.j], ps1 = psi[g.j + 1];
+    const P dp0 = dpsi[g.j], dp1 = dpsi[g.j + 1];
+    const P b0 = bt[g.j], b1 = bt[g.j + 1];
+    const P psig = (P(1.0) - g.t) * ps0 + g.t * ps1;
+    const P dpg = (P(1.0) - g.t) * dp0 + g.t * dp1;
+    const P bg = (P(1.0) - g.t) * b0 + g.t * b1;
+    P D = d0 + psig;
     const bool clamped = D < G.dmin;
     if (clamped) D = G.dmin;
-    const double px = s.px;
-    const double py = WARM ? s.py : 0.0;
-    const double p2 = px * px + py * py;
-    const double iD = 1.0 / D;
-    const double gam = (1.0 + p2 + D * D) * (0.5 * iD);
-    const double F = (gam * iD) * dpg - bg;
+    const P px = s.px;
+    const P py = WARM ? s.py : P(0.0);
+    const P p2 = px * px + py * py;
+    const P iD = P(1.0) / D;
+    const P gam = (P(1.0) + p2 + D * D) * (P(0.5) * iD);
+    const P F = (gam * iD) * dpg - bg;
 
-    double Fb = 0.0, rb = 0.0, xb = 0.0, yb = 0.0;
+    P Fb = P(0.0), rb = P(0.0);
+    double xb = 0.0, yb = 0.0;
     if (GEOM == WK_CYL) {
-        if (g.r > 0.0) {
-            const double fr = g.sw * F / g.r;
-            const double frb = fb.fpx * s.x + (WARM ? fb.fpy * s.y : 0.0);
+        if (g.r > P(0.0)) {
+            const P fr = g.sw * F / g.r;
+            const P frb = fb.fpx * s.x + (WARM ? fb.fpy * s.y : P(0.0));
             xb += fr * fb.fpx;
             if (WARM) yb += fr * fb.fpy;
             Fb = g.sw * frb / g.r;
@@ -173,24 +177,24 @@ __host__ __device__ inline DerAdj derivative_vjp(const St& s, double d0, const d
         Fb = g.sg * fb.fpx;
     }
     const bool has_y = GEOM == WK_CYL && WARM;
-    double iDb = fb.fx * px + (has_y ? fb.fy * py : 0.0);
-    double pxb = fb.fx * iD;
-    double pyb = has_y ? fb.fy * iD : 0.0;
-    const double gamb = Fb * iD * dpg;
+    P iDb = fb.fx * px + (has_y ? fb.fy * py : P(0.0));
+    P pxb = fb.fx * iD;
+    P pyb = has_y ? fb.fy * iD : P(0.0);
+    const P gamb = Fb * iD * dpg;
     iDb += Fb * gam * dpg;
-    const double dpgb = Fb * gam * iD;
-    const double bgb = -Fb;
-    const double p2b = gamb * 0.5 * iD;
-    const double Db = gamb * (0.5 - 0.5 * (1.0 + p2) * iD * iD) - iDb * iD * iD;
-    pxb += 2.0 * px * p2b;
-    if (WARM) pyb += 2.0 * py * p2b;
-    double psigb = 0.0;
+    const P dpgb = Fb * gam * iD;
+    const P bgb = -Fb;
+    const P p2b = gamb * P(0.5) * iD;
+    const P Db = gamb * (P(0.5) - P(0.5) * (P(1.0) + p2) * iD * iD) - iDb * iD * iD;
+    pxb += P(2.0) * px * p2b;
+    if (WARM) pyb += P(2.0) * py * p2b;
+    P psigb = P(0.0);
     if (!clamped) {
         psigb = Db;
         d0b += Db;
     }
-    const double tb = psigb * (ps1 - ps0) + dpgb * (dp1 - dp0) + bgb * (b1 - b0);
-    geo_vjp<GEOM, WARM>(s, g, G, tb, 0.0, rb, xb, yb);
+    const P tb = psigb * (ps1 - ps0) + dpgb * (dp1 - dp0) + bgb * (b1 - b0);
+    geo_vjp<GEOM, WARM, P>(s, g, G, tb, P(0.0), rb, xb, yb);
     sb.x += xb;
     sb.y += yb;
     sb.px += pxb;
@@ -209,39 +213,39 @@ __host__ __device__ inline DerAdj derivative_vjp(const St& s, double d0, const d
 // ---------------------------------------------------------------------------
 // c[0..6] = J_r, J_z, M1, M2, M3, M4, M5 contributions (before the hat
 // weights and the node volumes), as deposited by the march.
-template <int GEOM, bool WARM>
-__host__ __device__ inline Geo moment_terms(const St& s, double d0, double w, const double* psi, const Grid& G,
-                                            double c[7])
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline GeoT<P> moment_terms(const St& s, P d0, P w, const double* psi, const Grid& G,
+                                            P c[7])
 {
-    const Geo g = geo_of<GEOM, WARM>(s, G);
-    double D = d0 + hat_gather(psi, g);
+    const GeoT<P> g = geo_of<GEOM, WARM, P>(s, G);
+    P D = d0 + hat_gather<P>(psi, g);
     if (D < G.dmin) D = G.dmin;
-    const double px = s.px;
-    const double py = WARM ? s.py : 0.0;
-    const double p2 = px * px + py * py;
-    const double iD = 1.0 / D;
-    const double h2D = 0.5 * iD;
-    const double gam = (1.0 + p2 + D * D) * h2D;
-    const double pz = (1.0 + p2 - D * D) * h2D;
-    double pr;
+    const P px = s.px;
+    const P py = WARM ? s.py : P(0.0);
+    const P p2 = px * px + py * py;
+    const P iD = P(1.0) / D;
+    const P h2D = P(0.5) * iD;
+    const P gam = (P(1.0) + p2 + D * D) * h2D;
+    const P pz = (P(1.0) + p2 - D * D) * h2D;
+    P pr;
     if (GEOM == WK_CYL) {
         if (WARM)
-            pr = g.r > 0.0 ? g.sw * (s.x * px + s.y * py) * (1.0 / g.r) : 0.0;
+            pr = g.r > P(0.0) ? g.sw * (s.x * px + s.y * py) * (P(1.0) / g.r) : P(0.0);
         else
-            pr = g.r > 0.0 ? g.sw * (s.x * px) * (1.0 / g.r) : 0.0;
+            pr = g.r > P(0.0) ? g.sw * (s.x * px) * (P(1.0) / g.r) : P(0.0);
     } else {
         pr = g.sg * px;
     }
-    const double wiD = w * iD;
-    const double wiD2 = wiD * iD;
+    const P wiD = w * iD;
+    const P wiD2 = wiD * iD;
     c[0] = -wiD * pr;
     c[1] = -wiD * pz;
     c[2] = wiD;
     c[3] = wiD2 * (gam - pr * pr * iD);
-    c[4] = 0.0;
-    if (GEOM == WK_CYL && WARM && g.rho > 0.0) {
-        const double l = s.x * py - s.y * px;
-        const double ir = 1.0 / g.rho;
+    c[4] = P(0.0);
+    if (GEOM == WK_CYL && WARM && g.rho > P(0.0)) {
+        const P l = s.x * py - s.y * px;
+        const P ir = P(1.0) / g.rho;
         c[4] = wiD2 * (l * l) * (ir * ir * ir);
     }
     c[5] = wiD2 * pr;
@@ -253,55 +257,56 @@ __host__ __device__ inline Geo moment_terms(const St& s, double d0, double w, co
 // the particle, dr[r] = its difference across the cell (row[j+1] - row[j]).
 // Adds to sb, d0b, wb; returns the adjoint of the gathered psi (deposited
 // onto the psi adjoint row at the returned hat position).
-template <int GEOM, bool WARM>
-__host__ __device__ inline DerAdj moment_terms_vjp(const St& s, double d0, double w, const double* psi,
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline DerAdj moment_terms_vjp(const St& s, P d0, P w, const double* psi,
                                                    const Grid& G, const double gr[7], const double dr[7], St& sb,
                                                    double& d0b, double& wb)
 {
-    double c[7];
-    const Geo g = moment_terms<GEOM, WARM>(s, d0, w, psi, G, c);
-    const double ps0 = psi[g.j], ps1 = psi[g.j + 1];
-    double D = d0 + ((1.0 - g.t) * ps0 + g.t * ps1);
+    P c[7];
+    const GeoT<P> g = moment_terms<GEOM, WARM, P>(s, d0, w, psi, G, c);
+    const P ps0 = psi[g.j], ps1 = psi[g.j + 1];
+    P D = d0 + ((P(1.0) - g.t) * ps0 + g.t * ps1);
     const bool clamped = D < G.dmin;
     if (clamped) D = G.dmin;
-    const double px = s.px;
-    const double py = WARM ? s.py : 0.0;
-    const double p2 = px * px + py * py;
-    const double iD = 1.0 / D;
-    const double gam = (1.0 + p2 + D * D) * (0.5 * iD);
-    const double pz = (1.0 + p2 - D * D) * (0.5 * iD);
-    double pr;
+    const P px = s.px;
+    const P py = WARM ? s.py : P(0.0);
+    const P p2 = px * px + py * py;
+    const P iD = P(1.0) / D;
+    const P gam = (P(1.0) + p2 + D * D) * (P(0.5) * iD);
+    const P pz = (P(1.0) + p2 - D * D) * (P(0.5) * iD);
+    P pr;
     if (GEOM == WK_CYL) {
-        if (WARM) pr = g.r > 0.0 ? g.sw * (s.x * px + s.y * py) / g.r : 0.0;
-        else pr = g.r > 0.0 ? g.sw * (s.x * px) / g.r : 0.0;
+        if (WARM) pr = g.r > P(0.0) ? g.sw * (s.x * px + s.y * py) / g.r : P(0.0);
+        else pr = g.r > P(0.0) ? g.sw * (s.x * px) / g.r : P(0.0);
     } else {
         pr = g.sg * px;
     }
-    const bool m3 = GEOM == WK_CYL && WARM && g.rho > 0.0;
-    const double l = (GEOM == WK_CYL && WARM) ? s.x * py - s.y * px : 0.0;
-    const double ir = m3 ? 1.0 / g.rho : 0.0;
-    const double ir3 = ir * ir * ir;
+    const bool m3 = GEOM == WK_CYL && WARM && g.rho > P(0.0);
+    const P l = (GEOM == WK_CYL && WARM) ? s.x * py - s.y * px : P(0.0);
+    const P ir = m3 ? P(1.0) / g.rho : P(0.0);
+    const P ir3 = ir * ir * ir;
 
-    double tb = 0.0;
+    P tb = P(0.0);
     for (int r = 0; r < 7; ++r) tb += c[r] * dr[r];
-    const double iD2 = iD * iD;
+    const P iD2 = iD * iD;
     wb += -iD * pr * gr[0] - iD * pz * gr[1] + iD * gr[2] + iD2 * (gam - pr * pr * iD) * gr[3] +
           iD2 * l * l * ir3 * gr[4] + iD2 * pr * gr[5] + iD2 * pr * pr * gr[6];
-    const double iDb = -w * pr * gr[0] - w * pz * gr[1] + w * gr[2] +
-                       w * (2.0 * iD * gam - 3.0 * iD2 * pr * pr) * gr[3] + 2.0 * w * iD * l * l * ir3 * gr[4] +
-                       2.0 * w * iD * pr * gr[5] + 2.0 * w * iD * pr * pr * gr[6];
-    const double prb = -w * iD * gr[0] - 2.0 * w * iD2 * iD * pr * gr[3] + w * iD2 * gr[5] +
-                       2.0 * w * iD2 * pr * gr[6];
-    const double pzb = -w * iD * gr[1];
-    const double gamb = w * iD2 * gr[3];
-    const double lb = 2.0 * w * iD2 * l * ir3 * gr[4];
-    const double rhob_direct = m3 ? -3.0 * w * iD2 * l * l * ir3 * ir * gr[4] : 0.0;
+    const P iDb = -w * pr * gr[0] - w * pz * gr[1] + w * gr[2] +
+                       w * (P(2.0) * iD * gam - P(3.0) * iD2 * pr * pr) * gr[3] + P(2.0) * w * iD * l * l * ir3 * gr[4] +
+                       P(2.0) * w * iD * pr * gr[5] + P(2.0) * w * iD * pr * pr * gr[6];
+    const P prb = -w * iD * gr[0] - P(2.0) * w * iD2 * iD * pr * gr[3] + w * iD2 * gr[5] +
+                       P(2.0) * w * iD2 * pr * gr[6];
+    const P pzb = -w * iD * gr[1];
+    const P gamb = w * iD2 * gr[3];
+    const P lb = P(2.0) * w * iD2 * l * ir3 * gr[4];
+    const P rhob_direct = m3 ? -P(3.0) * w * iD2 * l * l * ir3 * ir * gr[4] : P(0.0);
 
-    const double p2b = 0.5 * iD * (gamb + pzb);
-    const double Db = gamb * (0.5 - 0.5 * (1.0 + p2) * iD2) + pzb * (-0.5 - 0.5 * (1.0 + p2) * iD2) - iDb * iD2;
-    double xb = 0.0, yb = 0.0, pxb = 2.0 * px * p2b, pyb = WARM ? 2.0 * py * p2b : 0.0, rb = 0.0;
+    const P p2b = P(0.5) * iD * (gamb + pzb);
+    const P Db = gamb * (P(0.5) - P(0.5) * (P(1.0) + p2) * iD2) + pzb * (-P(0.5) - P(0.5) * (P(1.0) + p2) * iD2) - iDb * iD2;
+    double xb = 0.0, yb = 0.0;
+    P pxb = P(2.0) * px * p2b, pyb = WARM ? P(2.0) * py * p2b : P(0.0), rb = P(0.0);
     if (GEOM == WK_CYL) {
-        if (g.r > 0.0) {
+        if (g.r > P(0.0)) {
             if (WARM) {
                 xb += g.sw * px / g.r * prb;
                 yb += g.sw * py / g.r * prb;
@@ -322,21 +327,21 @@ __host__ __device__ inline DerAdj moment_terms_vjp(const St& s, double d0, doubl
     } else {
         pxb += g.sg * prb;
     }
-    double psigb = 0.0;
+    P psigb = P(0.0);
     if (!clamped) {
         psigb = Db;
         d0b += Db;
         tb += Db * (ps1 - ps0);
     }
-    geo_vjp<GEOM, WARM>(s, g, G, tb, rhob_direct, rb, xb, yb);
+    geo_vjp<GEOM, WARM, P>(s, g, G, tb, rhob_direct, rb, xb, yb);
     sb.x += xb;
     sb.y += yb;
     sb.px += pxb;
     sb.py += pyb;
     DerAdj o;
     o.gpsi = psigb;
-    o.gdpsi = 0.0;
-    o.gb = 0.0;
+    o.gdpsi = P(0.0);
+    o.gb = P(0.0);
     o.j = g.j;
     o.t = g.t;
     return o;
@@ -344,14 +349,14 @@ __host__ __device__ inline DerAdj moment_terms_vjp(const St& s, double d0, doubl
 
 // Adjoint of the S deposit (weight w at the hat): gsb = S adjoint row
 // gathered at the particle, dsb = its difference across the cell.
-template <int GEOM, bool WARM>
-__host__ __device__ inline void s_term_vjp(const St& s, double w, const Grid& G, const double* sbar, St& sb, double& wb)
+template <int GEOM, bool WARM, typename P = double>
+__host__ __device__ inline void s_term_vjp(const St& s, P w, const Grid& G, const double* sbar, St& sb, double& wb)
 {
-    const Geo g = geo_of<GEOM, WARM>(s, G);
-    const double a0 = sbar[g.j], a1 = sbar[g.j + 1];
-    wb += (1.0 - g.t) * a0 + g.t * a1;
+    const GeoT<P> g = geo_of<GEOM, WARM, P>(s, G);
+    const P a0 = sbar[g.j], a1 = sbar[g.j + 1];
+    wb += (P(1.0) - g.t) * a0 + g.t * a1;
     double xb = 0.0, yb = 0.0;
-    geo_vjp<GEOM, WARM>(s, g, G, w * (a1 - a0), 0.0, 0.0, xb, yb);
+    geo_vjp<GEOM, WARM, P>(s, g, G, w * (a1 - a0), P(0.0), P(0.0), xb, yb);
     sb.x += xb;
     sb.y += yb;
 }
@@ -498,11 +503,12 @@ struct BeamCell {
 };
 
 // One Boris step of a beam particle in the fields (fez, fb, fw planes of
-// [n_xi][n_r + 1]); S = double or Dual.  When `seed` the field values get
-// the dual directions 6, 7, 8 (E_z, B_theta, W).
-template <typename S>
+// [n_xi][n_r + 1], stored as FT: double, or float for mixed plans); S =
+// double or Dual.  When `seed` the field values get the dual directions 6,
+// 7, 8 (E_z, B_theta, W).
+template <typename S, typename FT = double>
 __host__ __device__ inline BeamCell boris_step(int geom, int n_r, int n_xi, double r_max, double h, double xi_min,
-                                               double dxi, const double* fez, const double* fb, const double* fw,
+                                               double dxi, const FT* fez, const FT* fb, const FT* fw,
                                                S& x, S& y, S& xi, S& px, S& py, S& pz, double dt, bool seed)
 {
     const int N1 = n_r + 1;
@@ -528,9 +534,12 @@ __host__ __device__ inline BeamCell boris_step(int geom, int n_r, int n_xi, doub
         const S w00 = (one - tr) * (one - tk1), w01 = tr * (one - tk1);
         const S w10 = (one - tr) * tk1, w11 = tr * tk1;
         const int64_t o0 = (int64_t)k * N1 + j, o1 = (int64_t)k1 * N1 + j;
-        ez = w00 * S(fez[o0]) + w01 * S(fez[o0 + 1]) + w10 * S(fez[o1]) + w11 * S(fez[o1 + 1]);
-        bt = w00 * S(fb[o0]) + w01 * S(fb[o0 + 1]) + w10 * S(fb[o1]) + w11 * S(fb[o1 + 1]);
-        wv = w00 * S(fw[o0]) + w01 * S(fw[o0 + 1]) + w10 * S(fw[o1]) + w11 * S(fw[o1 + 1]);
+        ez = w00 * S((double)fez[o0]) + w01 * S((double)fez[o0 + 1]) + w10 * S((double)fez[o1]) +
+             w11 * S((double)fez[o1 + 1]);
+        bt = w00 * S((double)fb[o0]) + w01 * S((double)fb[o0 + 1]) + w10 * S((double)fb[o1]) +
+             w11 * S((double)fb[o1 + 1]);
+        wv = w00 * S((double)fw[o0]) + w01 * S((double)fw[o0 + 1]) + w10 * S((double)fw[o1]) +
+             w11 * S((double)fw[o1 + 1]);
         cell.inside = true;
         cell.j = j;
         cell.k = k;

@@ -794,14 +794,14 @@ wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from, 
 namespace {
 
 struct GradLayout {
-    size_t plan_ws, jb, tape, ckpt, hist, fbar, jbbar, scratch, ybar, d0bar, wbar, sb0, wbar_beam, wsum, partials;
+    size_t plan_ws, jb, tape, ckpt, hist, fbar, jbbar, scratch, ybar, d0bar, wbar, sb0, wbar_beam, wsum, partials,
+        d0_f64, w_f64;
     size_t total;
 };
 
 wk_status grad_check(const wk_plan* pl, int32_t n_steps, int32_t every)
 {
     if (!pl) return fail(WK_ERR_INVALID_ARG, "NULL plan");
-    if (pl->p.prec != WK_FP64) return fail(WK_ERR_UNSUPPORTED, "the gradient needs an FP64 plan");
     if (pl->p.n_bunch != 2 || pl->p.n_beam <= 0)
         return fail(WK_ERR_UNSUPPORTED, "the gradient needs a two-bunch beam of macroparticles");
     if (n_steps < 0) return fail(WK_ERR_INVALID_ARG, "n_steps must be >= 0");
@@ -839,6 +839,8 @@ GradLayout grad_layout(const wk_plan* pl, int32_t n_steps, int32_t every)
     L.wbar_beam = take(d * nb);
     L.wsum = take(d);
     L.partials = take(d * wk::theta_partials_doubles());
+    L.d0_f64 = take(pl->p.prec == WK_FP64 ? 0 : d * np);
+    L.w_f64 = take(pl->p.prec == WK_FP64 ? 0 : d * np);
     L.total = o;
     return L;
 }
@@ -880,9 +882,10 @@ wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma,
         e = wk::launch_init_plasma(g, plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec, *plasma, d_plasma_draws, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (load)");
     const wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
-    e = wk::launch_march_record(md, plan->threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt), every, s);
+    e = wk::launch_march_record(md, plan->p.prec, plan->threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt),
+                                every, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (march)");
-    e = wk::launch_push_record(g, plan->p.n_beam, *beam, (const double*)d_fields, n_steps, dt,
+    e = wk::launch_push_record(g, plan->p.n_beam, *beam, d_fields, plan->p.prec, n_steps, dt,
                                (double*)(ws + L.hist), (unsigned long long*)d_counters, s);
     const size_t gain_off = L.plan_ws + plan->ws_beam_off + wk::beam_ws_bytes(plan->p.n_xi, plan->p.n_beam) -
                             a256(sizeof(double) * 2 * 512);
@@ -919,7 +922,10 @@ wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma
     gd.sigma_r = plan->p.sigma_r;
     gd.sigma_zd = plan->p.bunch[0].sigma_z;
     gd.u_th = plan->p.u_th;
-    gd.fields = (const double*)d_fields;
+    gd.prec = plan->p.prec;
+    gd.fields = d_fields;
+    gd.d0_f64 = (double*)(ws + L.d0_f64);
+    gd.w_f64 = (double*)(ws + L.w_f64);
     gd.tape = (const double*)(ws + L.tape);
     gd.ckpt = (const double*)(ws + L.ckpt);
     gd.hist = (const double*)(ws + L.hist);

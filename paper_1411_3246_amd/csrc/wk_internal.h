@@ -206,7 +206,10 @@ struct GradDesc {
     int n_steps, every, threads;             // threads: workgroup size of the reverse march
     double dt;
     double n_d, sigma_r, sigma_zd, u_th;     // the parameters
-    const double* fields;        // [4][n_xi][N1] of the forward
+    int prec;                    // WK_FP64 or WK_MIXED (float fields and plasma constants)
+    const void* fields;          // real[4][n_xi][N1] of the forward
+    double* d0_f64;              // mixed: [np] plasma D0 and w as double (scratch)
+    double* w_f64;
     const double* tape;
     const double* ckpt;
     const double* hist;          // [n_steps + 1][6][n_beam]
@@ -229,9 +232,9 @@ size_t adjoint_lds_bytes(int n_nodes);
 size_t adjoint_tape_doubles(int n_xi, int n_nodes);
 size_t adjoint_scratch_doubles(int64_t np, int every, int threads);
 size_t theta_partials_doubles();
-hipError_t launch_march_record(const MarchDesc& d, int threads, double* tape, double* ckpt, int every,
+hipError_t launch_march_record(const MarchDesc& d, int prec, int threads, double* tape, double* ckpt, int every,
                                hipStream_t s);
-hipError_t launch_push_record(const GridDesc& g, int64_t n, const wk_beam_bufs& b, const double* fields,
+hipError_t launch_push_record(const GridDesc& g, int64_t n, const wk_beam_bufs& b, const void* fields, int prec,
                               int n_steps, double dt, double* hist, unsigned long long* counters, hipStream_t s);
 hipError_t launch_gradient_backward(const GradDesc& gd, hipStream_t s);
 

@@ -120,13 +120,63 @@ def test_autograd_function(W):
     assert np.allclose(dg.numpy(), 3.0 * grad, rtol=1e-12, atol=0.0)
 
 
+@pytest.mark.timeout(900)
 def test_gradient_case_full_size_weak_driver(O, W):
     """The 256 x 2048, 16 ppc, 2e5-particle, 20-step gradient workload (weak
-    driver, checkpoints every 64 slices): drive density, drive length and
-    separation derivatives against the oracle's finite differences."""
+    driver, u_th = 0.005, checkpoints every 64 slices): all five components
+    against the oracle's finite differences."""
     p = inputs.gradient_case(n_d=0.1).replace(u_th=0.005)
     print(f"case {p.name} n_d=0.1", flush=True)
     g, grad, run = _gpu(W, p, every=64)
     assert g == pytest.approx(O.objective(p), rel=1e-10)
-    fd, err = _fd(O, p, (0, 2, 3))
-    _compare(grad, fd, err, (0, 2, 3))
+    which = (0, 1, 2, 3, 4)
+    fd, err = _fd(O, p, which)
+    _compare(grad, fd, err, which)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n_d=1.0, u_th=0.01), dict(geom="slab", r_max=8.0, u_th=0.005)],
+                         ids=["weak-warm", "moderate", "slab"])
+def test_mixed_adjoint_matches_fp64_finite_differences(O, W, kw):
+    """The gradient of a mixed plan (float recorded march and float
+    per-particle adjoint arithmetic) against the FP64 oracle's finite
+    differences: every component within 2e-3 of its value, the objective
+    within 1e-3 of the FP64 one (the bar of the mixed fields: float
+    per-particle arithmetic moves the fields by about 1e-5-1e-4)."""
+    p = _case(**kw).replace(prec="mixed")
+    print(f"case mixed {kw}", flush=True)
+    g, grad, run = _gpu(W, p)
+    q = p.replace(prec="fp64")
+    g64 = O.objective(q)
+    print(f"  objective mixed {g:.10e} fp64 {g64:.10e}", flush=True)
+    assert g == pytest.approx(g64, rel=1e-3)
+    which = (0, 1, 2, 3, 4) if p.u_th > 0 else (0, 1, 2, 3)
+    fd, err = _fd(O, q, which)
+    for i in which:
+        print(f"  {inputs.THETA_NAMES[i]:>14s} mixed adjoint {grad[i]: .10e} fp64 fd {fd[i]: .10e} "
+              f"rel {abs(grad[i] - fd[i]) / max(abs(fd[i]), 1e-30):.2e}", flush=True)
+    c = W.counters_dict(run.counters)
+    assert c["nonfinite"] == 0
+    for i in which:
+        assert abs(grad[i] - fd[i]) <= 2e-3 * abs(fd[i]) + 1e-10 * max(abs(fd[k]) for k in which), \
+            (inputs.THETA_NAMES[i], grad[i], fd[i])
+
+
+@pytest.mark.timeout(900)
+def test_mixed_gradient_full_size(O, W):
+    """The 256 x 2048, 16 ppc, 2e5-particle, 20-step gradient workload in
+    mixed precision (weak driver, u_th = 0.005, checkpoints every 64 slices):
+    all five components against the FP64 oracle's finite differences
+    within 2e-3, the objective within 1e-3."""
+    p = inputs.gradient_case(n_d=0.1).replace(u_th=0.005, prec="mixed")
+    print(f"case {p.name} mixed n_d=0.1", flush=True)
+    g, grad, run = _gpu(W, p, every=64)
+    q = p.replace(prec="fp64")
+    assert g == pytest.approx(O.objective(q), rel=1e-3)
+    which = (0, 1, 2, 3, 4)
+    fd, err = _fd(O, q, which)
+    for i in which:
+        print(f"  {inputs.THETA_NAMES[i]:>14s} mixed adjoint {grad[i]: .10e} fp64 fd {fd[i]: .10e} "
+              f"rel {abs(grad[i] - fd[i]) / max(abs(fd[i]), 1e-30):.2e}", flush=True)
+    for i in which:
+        assert abs(grad[i] - fd[i]) <= 2e-3 * abs(fd[i]) + 1e-10 * max(abs(fd[k]) for k in which), \
+            (inputs.THETA_NAMES[i], grad[i], fd[i])
