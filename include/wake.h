@@ -274,8 +274,13 @@ int32_t wk_plan_group(const wk_plan* plan);
  *      its slice of the workspace), longest instances first;
  *   2. the caller copies the blob to device memory;
  *   3. wk_batch_response marches every instance in one persistent launch:
- *      workgroups take instances from a work queue in the workspace.
- * h_* arrays have n entries; d_workspace has wk_batch_workspace_size bytes. */
+ *      each instance by a group of workgroups (enough to hold its particles
+ *      in registers and to bring its cost near the per-compute-unit average
+ *      of the batch, at most 16), the workgroups taking tickets (one member
+ *      of one instance's group) from a queue in the workspace, longest
+ *      instances first.
+ * h_* arrays have n entries; d_workspace has wk_batch_workspace_size bytes;
+ * a plan's group (wk_plan_set_group) overrides the choice for its instance. */
 size_t wk_batch_desc_bytes(int32_t n);
 size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans);
 wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans,
@@ -296,9 +301,11 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
 /* The quasi-static cycle, n_steps times: beam current from the macroparticles
  * -> plasma response -> beam advance by dt (Section II A: the plasma responds
  * to the frozen beam, then the beam is advanced in t).  The responses of
- * successive steps run concurrently on separate workgroups: response n
- * marches slice k once response n-1 has stored the slices up to k + 2, and
- * advances the beam particles of each xi bin just before it deposits them.
+ * successive steps run concurrently on separate groups of workgroups
+ * (wk_cycle_group; each member of a group owns a band of the plasma cells
+ * and a contiguous subset of the beam): response n marches slice k once
+ * response n-1 has stored the slices up to k + 2, and advances the beam
+ * particles of each xi bin just before it deposits them.
  * The result equals n_steps sequential calls of wk_beam_current,
  * wk_plasma_response (from the same loaded plasma) and wk_beam_push(1 step)
  * up to the summation order of the deposits.
@@ -306,11 +313,13 @@ wk_status wk_batch_response_shape(int32_t n, const wk_plan* const* h_plans, cons
  *   d_ring:   2 * sizes.fields bytes; the fields of response n are in slot
  *             n % 2, so the last response is in slot (n_steps - 1) % 2
  *   workspace: wk_cycle_workspace_size(plan, n_steps) bytes.
- * Any n_r up to 2048: beyond about 880 cells the node rows and the beam
- * current rows live in the workspace instead of LDS.  Counter
- * WK_CNT_PIPELINE_ABORT is set if a workgroup waited too long for its
- * predecessor (then the results are invalid); WK_CNT_BEAM_BIN counts
- * particles whose xi moved by more than a slice during the run. */
+ * Any n_r up to 2048: beyond about 880 cells the field and solver node rows
+ * live in the workspace and the beam current is deposited straight into the
+ * LDS current row instead of an LDS ring of rows.  Counter
+ * WK_CNT_PIPELINE_ABORT is set if a workgroup waited too long for another
+ * (then the results are invalid); WK_CNT_BEAM_BIN counts particles whose xi
+ * moved by more than a slice during the run (or that were found ahead of the
+ * window); WK_CNT_BEAM_ORDER is set if a subset's bins lost particles. */
 size_t wk_cycle_workspace_size(const wk_plan* plan, int32_t n_steps);
 /* Workgroups per response that wk_cycle uses for n_steps steps on the
  * current device: the plan's group when set, else the largest group for

@@ -147,3 +147,42 @@ def test_full_scan_sampled_against_oracle(O, W):
     # first slice: the plasma is unperturbed, so psi, E_z and W vanish there
     for k in (0, 1, 3):
         assert np.max(np.abs(f[k, 0])) <= 1e-6 * max(np.max(np.abs(f[k])), 1e-30), k
+
+
+def test_scan_tuning_is_cached(W, tmp_path):
+    """A batch tuned once takes its cached shape the next time."""
+    from paper_1411_3246_amd import autotune
+    cache = autotune.TuneCache(str(tmp_path / "tune.json"))
+    scan = W.Scan(small_scan())
+    best, table = autotune.tune_scan(scan, candidates=autotune.CANDIDATES[:2], cache=cache)
+    assert not any(r.get("cached") for r in table)
+    other = W.Scan(small_scan())
+    best2, table2 = autotune.tune_scan(other, cache=autotune.TuneCache(cache.path))
+    assert best2 == best and (other.threads, other.wg_per_cu) == best
+    assert all(r["cached"] for r in table2)
+
+
+def test_response_tuning_per_class(O, W, tmp_path):
+    """The standalone response tuned for (n_r, ppc, precision, geometry,
+    temperature) on a short window: the choice is cached for the class, a
+    second call takes it from the cache, and a response launched with it
+    equals the oracle within 1e-10."""
+    import torch
+    from paper_1411_3246_amd import autotune
+    cache = autotune.TuneCache(str(tmp_path / "tune.json"))
+    p = inputs.facet_two_bunch(n_r=128, n_xi=200, ppc=8, u_th=0.02, n_d=1.0, n_beam=0, prec="fp64",
+                               name="tune-128")
+    choice, table, hit = autotune.tune_response(p, cache, window=48, threads=(256, 512), groups=(1, 2, 4))
+    print("tuned", choice, table, flush=True)
+    assert not hit and len(table) == 6 and all(r["ms_per_slice"] > 0 for r in table)
+    again, _, hit = autotune.tune_response(p.replace(n_xi=400, xi_max=p.xi_min + 400 * p.dxi), cache)
+    assert hit and again == choice
+    assert autotune.cached_response(p, autotune.TuneCache(cache.path)) == choice
+    ref = O.response(p, inputs.plasma_draws(p))
+    sim = W.Simulation(p, threads=choice[0], group=choice[1])
+    sim.jb.copy_(torch.from_numpy(np.ascontiguousarray(ref["jb"])))
+    sim.response()
+    torch.cuda.synchronize()
+    assert (sim.plan.threads, sim.plan.group) == choice
+    for i in range(4):
+        assert _rel(_np(sim.fields[i]), ref["fields"][i]) <= 1e-10, i
