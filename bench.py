@@ -166,7 +166,7 @@ def cpu_baseline(p, fraction: float):
 def scan_bench(args, log):
     """The batched parameter scan: every instance of the scan marched in one
     persistent launch (each instance by a group of workgroups sized to its
-    cost, shape picked by the autotuner, the whole pass replayed from a HIP
+    cost, schedule picked by the autotuner, the whole pass replayed from a HIP
     graph), against the roofline and against the same instances run one
     standalone response at a time (each with its own group).
 
@@ -178,6 +178,7 @@ def scan_bench(args, log):
     probs = inputs.scan_instances(args.scan_instances)
     scan = wake.Scan(probs)
     best, table = autotune.tune_scan(scan, log=log)
+    groups = scan.groups
     scan.capture()
     stream = torch.cuda.current_stream()
     scan.replay()
@@ -227,7 +228,8 @@ def scan_bench(args, log):
         "batched_speedup": seq_ms / batched_ms,
         "standalone_scaling_check": [{"instance": probs[i].name, "whole_ms": w, "scaled_ms": est[i]}
                                      for i, w in zip(check_idx, whole)],
-        "shape": {"threads": best[0], "wg_per_cu": best[1]},
+        "schedule": {"member_cap": best[0], "wg_per_cu": best[1], "workgroups": sum(groups),
+                     "max_group": max(groups)},
         "tuner": table,
         "graph": True,
         "counters": counters,

@@ -283,6 +283,9 @@ int32_t wk_plan_group(const wk_plan* plan);
  * a plan's group (wk_plan_set_group) overrides the choice for its instance. */
 size_t wk_batch_desc_bytes(int32_t n);
 size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans);
+/* Workgroups that march instance i (0-based, in the order of h_plans) under
+ * the batch's schedule; 0 for a bad argument. */
+int32_t wk_batch_group(int32_t n, const wk_plan* const* h_plans, int32_t i);
 wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans,
                             const wk_plasma_bufs* h_plasma, const double* const* h_jb,
                             void* const* h_fields, void* d_workspace, size_t workspace_bytes,

@@ -11,9 +11,11 @@ launch stream, and cached:
   deposit, solves, exchanges) does not depend on where the slice is.  The
   pipelined cycle keeps its own choice, which also weighs how many responses
   run at once.
-* The batched scan: the workgroup size and the workgroups per compute unit of
-  its one persistent launch, cached per batch (the multiset of its instance
-  classes).
+* The batched scan: the schedule of its one persistent launch, i.e. the most
+  particles a workgroup may hold (which sets how many workgroups march each
+  instance and the launch shape that fits the largest share: 8192 the
+  1024x8 shape, 4096 the 512x8, 2048 the 512x4) and the workgroups per
+  compute unit; cached per batch (the multiset of its instance classes).
 
 Results depend on the choice only through the summation order of the LDS
 deposits.  The cache is a JSON file, by default
@@ -27,7 +29,8 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1))
+# (member cap, workgroups per CU; 0 = as many as fit)
+CANDIDATES: Tuple[Tuple[int, int], ...] = ((8192, 0), (4096, 0), (4096, 1), (2048, 0), (2048, 1))
 RESPONSE_THREADS: Tuple[int, ...] = (256, 512, 1024)
 RESPONSE_GROUPS: Tuple[int, ...] = (1, 2, 4, 8, 16)
 
@@ -134,11 +137,13 @@ def cached_response(p, cache: TuneCache) -> Optional[Tuple[int, int]]:
     return None if hit is None else (hit["threads"], hit["group"])
 
 
-def time_scan(scan, threads: int, wg_per_cu: int, repeats: int = 1) -> float:
-    """Milliseconds of one batched pass (plasma loads + march) with a shape."""
+def time_scan(scan, member_cap: int, wg_per_cu: int, repeats: int = 1) -> float:
+    """Milliseconds of one batched pass (plasma loads + march) with a
+    schedule."""
     import torch
     stream = torch.cuda.current_stream()
-    scan.threads, scan.wg_per_cu = threads, wg_per_cu
+    scan.set_member_cap(member_cap)
+    scan.threads, scan.wg_per_cu = 0, wg_per_cu
     scan.run()                                   # warm-up (kernel attributes, caches)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -162,25 +167,27 @@ def scan_key(problems: Sequence) -> str:
 def tune_scan(scan, candidates: Optional[Iterable[Tuple[int, int]]] = None,
               repeats: int = 1, log=None, cache: Optional[TuneCache] = None,
               force: bool = False) -> Tuple[Tuple[int, int], List[dict]]:
-    """Time every candidate (threads, workgroups per CU) on `scan`, set the
-    fastest on it and return it with the table of timings; with a cache, a
-    batch tuned before takes its cached shape (table marked cached)."""
+    """Time every candidate (member cap, workgroups per CU) on `scan`, set
+    the fastest on it and return it with the table of timings; with a cache,
+    a batch tuned before takes its cached schedule (table marked cached)."""
     key = scan_key(scan.problems)
     if cache is not None and not force:
         hit = cache.get(key)
         if hit is not None:
-            scan.threads, scan.wg_per_cu = hit["threads"], hit["wg_per_cu"]
-            return (hit["threads"], hit["wg_per_cu"]), [dict(r, cached=True) for r in hit.get("table", [])]
+            scan.set_member_cap(hit["member_cap"])
+            scan.threads, scan.wg_per_cu = 0, hit["wg_per_cu"]
+            return (hit["member_cap"], hit["wg_per_cu"]), [dict(r, cached=True) for r in hit.get("table", [])]
     table = []
-    for threads, per_cu in (candidates or CANDIDATES):
-        ms = time_scan(scan, threads, per_cu, repeats)
-        row = {"threads": threads, "wg_per_cu": per_cu, "ms": ms}
+    for cap, per_cu in (candidates or CANDIDATES):
+        ms = time_scan(scan, cap, per_cu, repeats)
+        row = {"member_cap": cap, "wg_per_cu": per_cu, "ms": ms, "workgroups": sum(scan.groups)}
         table.append(row)
         if log is not None:
             log(row)
     best = min(table, key=lambda r: r["ms"])
-    scan.threads, scan.wg_per_cu = best["threads"], best["wg_per_cu"]
+    scan.set_member_cap(best["member_cap"])
+    scan.threads, scan.wg_per_cu = 0, best["wg_per_cu"]
     if cache is not None:
-        cache.put(key, {"threads": best["threads"], "wg_per_cu": best["wg_per_cu"], "table": table,
+        cache.put(key, {"member_cap": best["member_cap"], "wg_per_cu": best["wg_per_cu"], "table": table,
                         "device": _device_name()})
-    return (best["threads"], best["wg_per_cu"]), table
+    return (best["member_cap"], best["wg_per_cu"]), table

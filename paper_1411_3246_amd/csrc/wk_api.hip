@@ -529,6 +529,12 @@ size_t wk_batch_workspace_size(int32_t n, const wk_plan* const* h_plans)
     return batch_schedule(n, h_plans).ws;
 }
 
+int32_t wk_batch_group(int32_t n, const wk_plan* const* h_plans, int32_t i)
+{
+    if (i < 0 || i >= n || wk_batch_workspace_size(n, h_plans) == 0) return 0;
+    return batch_schedule(n, h_plans).group[i];
+}
+
 wk_status wk_batch_describe(int32_t n, const wk_plan* const* h_plans, const wk_plasma_bufs* h_plasma,
                             const double* const* h_jb, void* const* h_fields, void* d_workspace,
                             size_t workspace_bytes, uint64_t* d_counters, void* h_desc)

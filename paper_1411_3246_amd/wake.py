@@ -65,7 +65,7 @@ EXPORTS = [
     "wk_version", "wk_status_string", "wk_plan_create", "wk_plan_destroy", "wk_plan_sizes",
     "wk_last_error", "wk_counters_zero", "wk_counters_read", "wk_init_plasma", "wk_init_beam",
     "wk_beam_current_analytic", "wk_beam_current", "wk_plasma_response", "wk_plan_set_threads",
-    "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_describe",
+    "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size", "wk_batch_group", "wk_batch_describe",
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle", "wk_plan_set_group", "wk_plan_group", "wk_cycle_group",
     "wk_plasma_response_noalloc", "wk_plasma_response_traj", "wk_gain_histogram",
@@ -119,6 +119,8 @@ def lib():
     L.wk_batch_desc_bytes.restype = C.c_size_t
     L.wk_batch_workspace_size.argtypes = [i32, C.POINTER(vp)]
     L.wk_batch_workspace_size.restype = C.c_size_t
+    L.wk_batch_group.argtypes = [i32, C.POINTER(vp), i32]
+    L.wk_batch_group.restype = i32
     L.wk_batch_describe.argtypes = [i32, C.POINTER(vp), C.POINTER(WkPlasmaBufs), C.POINTER(vp),
                                     C.POINTER(vp), vp, C.c_size_t, vp, vp]
     L.wk_batch_response.argtypes = [i32, C.POINTER(vp), vp, vp, C.c_size_t, vp]
@@ -208,7 +210,12 @@ class Plan:
         return lib().wk_plan_group(self.handle)
 
     def set_group(self, group: int):
+        """Workgroups per response (0: the library's choice); the workspace
+        size is updated."""
         _check(lib().wk_plan_set_group(self.handle, group), "wk_plan_set_group")
+        sz = WkSizes()
+        _check(lib().wk_plan_sizes(self.handle, C.byref(sz)), "wk_plan_sizes")
+        self.sizes = sz
 
     def cycle_group(self, n_steps: int) -> int:
         """Workgroups per response that wk_cycle uses for n_steps steps."""
@@ -548,7 +555,41 @@ class Scan:
         self.batch.describe(self.plasma, self.jb, self.fields, self.counters)
         self.threads = 0
         self.wg_per_cu = 0
+        self.member_cap = 0
         self.graph = None
+
+    def set_member_cap(self, cap: int):
+        """Re-plan the batch so that no workgroup holds more than `cap`
+        particles: instance i gets G_i = max(ceil(n_p / cap), ceil(cost_i /
+        (total cost / compute units))) workgroups, at most 16 and n_r, with
+        cost = n_p n_xi.  cap = 0 restores the library's schedule (the same
+        rule with cap 8192).  Drops a captured graph."""
+        import math
+        import torch
+        if cap < 0:
+            raise WakeError("member cap must be >= 0")
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        total = sum(float(q.n_plasma) * q.n_xi for q in self.problems)
+        per_cu = total / max(1, cus)
+        for q, pl in zip(self.problems, self.plans):
+            if cap == 0:
+                pl.set_group(0)
+                continue
+            g = max(math.ceil(q.n_plasma / cap), math.ceil(float(q.n_plasma) * q.n_xi / per_cu))
+            pl.set_group(max(1, min(g, 16, q.n_r)))
+        ws = max(pl.sizes.workspace for pl in self.plans)
+        if ws > self.workspace.numel():
+            self.workspace = torch.zeros(ws, dtype=torch.uint8, device=self.device)
+        self.batch = Batch(self.plans, self.device)
+        self.batch.describe(self.plasma, self.jb, self.fields, self.counters)
+        self.member_cap = cap
+        self.graph = None
+
+    @property
+    def groups(self) -> List[int]:
+        """Workgroups per instance of the current schedule (plan choice or
+        the library's)."""
+        return [int(lib().wk_batch_group(len(self.plans), self.batch._handles, i)) for i in range(len(self.plans))]
 
     @property
     def updates(self) -> int:

@@ -65,15 +65,22 @@ def test_scan_matches_oracle_every_shape(O, W, refs):
     import torch
     from paper_1411_3246_amd import autotune
     scan = W.Scan(small_scan())
-    for threads, per_cu in autotune.CANDIDATES:
-        print(f"shape threads={threads} wg_per_cu={per_cu}", flush=True)
+    shapes = [(0, threads, per_cu) for threads, per_cu in ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1))]
+    shapes += [(cap, 0, per_cu) for cap, per_cu in autotune.CANDIDATES] + [(64, 0, 0)]
+    for cap, threads, per_cu in shapes:
+        print(f"schedule cap={cap} threads={threads} wg_per_cu={per_cu}", flush=True)
+        scan.set_member_cap(cap)
         scan.threads, scan.wg_per_cu = threads, per_cu
         for f in scan.fields:
             f.zero_()
         scan.run()
         torch.cuda.synchronize()
         for q, f, ref in zip(scan.problems, scan.fields, refs):
-            assert _rel(_np(f), ref["fields"]) <= 1e-10, (q.name, threads, per_cu)
+            assert _rel(_np(f), ref["fields"]) <= 1e-10, (q.name, cap, threads, per_cu)
+        if cap == 64:
+            # members of at most 64 particles where 16 workgroups and n_r allow
+            for q, g in zip(scan.problems, scan.groups):
+                assert min(16, q.n_r, -(-q.n_plasma // 64)) <= g <= min(16, q.n_r), (q.name, g)
     c = W.counters_dict(scan.counters)
     assert c["nonfinite"] == 0
 
@@ -93,8 +100,11 @@ def test_autotuner_picks_a_valid_shape(O, W, refs):
     from paper_1411_3246_amd import autotune
     scan = W.Scan(small_scan())
     best, table = autotune.tune_scan(scan)
-    assert best in autotune.CANDIDATES
+    assert best in autotune.CANDIDATES and scan.member_cap == best[0]
     assert len(table) == len(autotune.CANDIDATES) and all(r["ms"] > 0 for r in table)
+    # the schedules differ: smaller members mean more workgroups
+    work = {r["member_cap"]: r["workgroups"] for r in table}
+    assert work[2048] >= work[4096] >= work[8192]
     scan.run()
     torch.cuda.synchronize()
     for q, f, ref in zip(scan.problems, scan.fields, refs):
@@ -158,7 +168,7 @@ def test_scan_tuning_is_cached(W, tmp_path):
     assert not any(r.get("cached") for r in table)
     other = W.Scan(small_scan())
     best2, table2 = autotune.tune_scan(other, cache=autotune.TuneCache(cache.path))
-    assert best2 == best and (other.threads, other.wg_per_cu) == best
+    assert best2 == best and (other.member_cap, other.wg_per_cu) == best
     assert all(r["cached"] for r in table2)
 
 
