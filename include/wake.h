@@ -225,6 +225,26 @@ wk_status wk_plasma_response_traj(const wk_plan* plan, const wk_plasma_bufs* pla
                                   int32_t stride, double* d_traj, uint64_t* d_counters,
                                   void* stream);
 
+/* The plasma response with B_theta from Eq. (6) as written, (1/r) d_r (r B)
+ * = d_xi E_z + J_z (slab: d_x B = d_xi E_z + J_z), integrated from the axis
+ * by the trapezoid rule, instead of its Helmholtz form: the cross-check of
+ * that reading (Section II A, Eqs. (6)-(7)).  d_xi E_z at slice k is the
+ * implicit one-sided (E_z,k+1 - E_z,k) / dxi (the last slice: the backward
+ * difference), and E_z,k+1 depends on B_k through the Heun step, so B_k is
+ * found by at most `iters` (1..64) Newton steps per slice on the fixed point
+ * of that step, each solved by GMRES (at most 40 Krylov vectors) with a
+ * finite-difference Jacobian, until max |Phi(B) - B| <= tol max |Phi(B)|
+ * (tol > 0).  First order in dxi.  FP64 plans, n_r up to 512 (its rows are
+ * kept in LDS), one workgroup per call (WK_ERR_UNSUPPORTED otherwise).
+ * d_workspace: wk_direct_workspace_size(plan) bytes, 8-byte aligned.
+ * d_iterations: optional int32[n_xi] of Newton steps used per slice.  The
+ * other arguments as for wk_plasma_response. */
+size_t wk_direct_workspace_size(const wk_plan* plan);
+wk_status wk_plasma_response_direct(const wk_plan* plan, const wk_plasma_bufs* plasma,
+                                    const double* d_jb, void* d_fields, void* d_workspace,
+                                    size_t workspace_bytes, int32_t iters, double tol,
+                                    int32_t* d_iterations, uint64_t* d_counters, void* stream);
+
 /* Bytes of the library's static device scratch array (one per device). */
 #define WK_NOALLOC_SCRATCH_BYTES (8u << 20)
 

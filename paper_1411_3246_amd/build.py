@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwake.so")
 # the march and cycle kernels are instantiated per precision and geometry in
 # separate translation units so that they compile in parallel
-SOURCES = ["wk_march.hip", "wk_beam.hip", "wk_adjoint.hip", "wk_api.hip"] + [
+SOURCES = ["wk_march.hip", "wk_beam.hip", "wk_adjoint.hip", "wk_direct.hip", "wk_api.hip"] + [
     f"wk_{kind}_{prec}_{geom}.hip" for kind in ("march", "cycle") for prec in ("f64", "f32")
     for geom in ("cyl", "slab")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

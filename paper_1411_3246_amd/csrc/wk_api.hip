@@ -441,6 +441,43 @@ wk_status wk_plasma_response_traj(const wk_plan* plan, const wk_plasma_bufs* pla
                        (hipStream_t)stream, d_traj, stride);
 }
 
+size_t wk_direct_workspace_size(const wk_plan* plan)
+{
+    if (!plan) return 0;
+    return a256(wk::direct_ws_doubles(plan->np, plan->N1) * sizeof(double));
+}
+
+wk_status wk_plasma_response_direct(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb,
+                                    void* d_fields, void* d_workspace, size_t workspace_bytes, int32_t iters,
+                                    double tol, int32_t* d_iterations, uint64_t* d_counters, void* stream)
+{
+    if (!plan || !d_jb || !d_fields || !d_workspace || !d_counters) return fail(WK_ERR_INVALID_ARG, "NULL argument");
+    if (plan->p.prec != WK_FP64) return fail(WK_ERR_UNSUPPORTED, "the Eq. (6)-direct response is FP64 only");
+    if (iters < 1 || iters > 64) return fail(WK_ERR_INVALID_ARG, "iters must be 1..64 (got %d)", iters);
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WK_ERR_INVALID_ARG, "tol must be finite and > 0");
+    if (!wk::lds_fits(wk::direct_lds_bytes(plan->N1)))
+        return fail(WK_ERR_UNSUPPORTED, "the Eq. (6)-direct response keeps its rows in LDS: n_r = %d is too large",
+                    plan->N);
+    const size_t need = wk_direct_workspace_size(plan);
+    if (workspace_bytes < need) return fail(WK_ERR_BUFFER, "direct workspace needs %zu bytes", need);
+    if (!aligned8(d_workspace) || (d_iterations && ((uintptr_t)d_iterations & 3)))
+        return fail(WK_ERR_BUFFER, "workspace or iterations buffer misaligned");
+    wk_status st = check_plasma(plan, plasma);
+    if (st != WK_OK) return st;
+    wk::DirectDesc dd{};
+    dd.march = make_desc(plan, plasma, d_jb, d_fields, d_counters);
+    const int64_t n4 = std::max<int64_t>(plan->np, 1) * 4;
+    double* ws = (double*)d_workspace;
+    dd.ys = ws;
+    dd.yn = ws + n4;
+    dd.f0 = ws + 2 * n4;
+    dd.V = ws + 3 * n4;
+    dd.iters = iters;
+    dd.tol = tol;
+    dd.iterations = d_iterations;
+    return hip_status(wk::launch_march_direct(dd, (hipStream_t)stream), "Eq. (6)-direct response");
+}
+
 wk_status wk_plasma_response_noalloc(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_jb,
                                      void* d_fields, uint64_t* d_counters, void* stream)
 {

@@ -69,12 +69,14 @@ EXPORTS = [
     "wk_batch_response", "wk_batch_response_shape", "wk_beam_push", "wk_mean_gain", "wk_ez_peak",
     "wk_cycle_workspace_size", "wk_cycle", "wk_plan_set_group", "wk_plan_group", "wk_cycle_group",
     "wk_plasma_response_noalloc", "wk_plasma_response_traj", "wk_gain_histogram",
+    "wk_direct_workspace_size", "wk_plasma_response_direct",
     "wk_gradient_workspace_size", "wk_gradient_forward", "wk_gradient_backward",
 ]
 
 _NON_STATUS = {"wk_version", "wk_status_string", "wk_last_error", "wk_plan_destroy",
                "wk_plan_threads", "wk_batch_desc_bytes", "wk_batch_workspace_size",
-               "wk_cycle_workspace_size", "wk_gradient_workspace_size", "wk_plan_group", "wk_cycle_group"}
+               "wk_cycle_workspace_size", "wk_gradient_workspace_size", "wk_plan_group", "wk_cycle_group",
+               "wk_direct_workspace_size", "wk_batch_group"}
 
 _lib = None
 
@@ -115,6 +117,10 @@ def lib():
     L.wk_plasma_response_noalloc.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, vp]
     L.wk_plasma_response_traj.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, i32, vp, vp, vp]
     L.wk_gain_histogram.argtypes = [vp, C.POINTER(WkBeamBufs), i32, i32, d, d, vp, vp]
+    L.wk_direct_workspace_size.argtypes = [vp]
+    L.wk_direct_workspace_size.restype = C.c_size_t
+    L.wk_plasma_response_direct.argtypes = [vp, C.POINTER(WkPlasmaBufs), vp, vp, vp, C.c_size_t, i32, d, vp, vp,
+                                            vp]
     L.wk_batch_desc_bytes.argtypes = [i32]
     L.wk_batch_desc_bytes.restype = C.c_size_t
     L.wk_batch_workspace_size.argtypes = [i32, C.POINTER(vp)]
@@ -312,6 +318,17 @@ class Plan:
                                              int(stride), _ptr(traj), _ptr(counters), _stream(stream)),
                "wk_plasma_response_traj")
 
+    def plasma_response_direct(self, plasma: Dict, jb, fields, workspace, counters, iters: int = 8,
+                               tol: float = 1e-10, iterations=None, stream=None):
+        """The response with B_theta from Eq. (6) as written (Newton-GMRES per
+        slice on the implicit d_xi E_z); workspace of wk_direct_workspace_size
+        bytes; iterations: optional int32[n_xi] of Newton steps per slice."""
+        b = self.plasma_bufs(plasma)
+        _check(lib().wk_plasma_response_direct(self.handle, C.byref(b), _ptr(jb), _ptr(fields), _ptr(workspace),
+                                               workspace.numel() * workspace.element_size(), int(iters),
+                                               float(tol), _ptr(iterations), _ptr(counters), _stream(stream)),
+               "wk_plasma_response_direct")
+
     def gain_histogram(self, beam: Dict, which: int, n_bins: int, lo: float, hi: float, hist, stream=None):
         """Counts of gamma - gamma_init in n_bins bins of [lo, hi) (+ under/overflow)."""
         b = self.beam_bufs(beam)
@@ -465,6 +482,17 @@ class Simulation:
         self.plan.plasma_response_traj(self.plasma, self.jb, self.fields, self.workspace, stride, traj,
                                        self.counters)
         return traj
+
+    def response_direct(self, iters: int = 8, tol: float = 1e-10):
+        """response() with B_theta from Eq. (6) as written; returns the Newton
+        steps used per slice (int32 tensor of n_xi)."""
+        import torch
+        dev = self.jb.device
+        ws = torch.zeros(lib().wk_direct_workspace_size(self.plan.handle), dtype=torch.uint8, device=dev)
+        its = torch.zeros(self.problem.n_xi, dtype=torch.int32, device=dev)
+        self.plan.init_plasma(self.plasma, self.plasma_draws)
+        self.plan.plasma_response_direct(self.plasma, self.jb, self.fields, ws, self.counters, iters, tol, its)
+        return its
 
     def gain_histogram(self, which: int, n_bins: int, lo: float, hi: float):
         """Energy spectrum of the beam (tag == which; all if which < 0): counts
