@@ -49,6 +49,8 @@ FLOPS_PER_UPDATE = 190.0
 PROFILES = os.path.join(ROOT, "profiles")
 CYCLE_COUNTERS = os.path.join(PROFILES, "k_cycle_two-bunch-512x4096-ppc16-beam1e6.counters.json")
 SCAN_COUNTERS = os.path.join(PROFILES, "k_march_batch_scan-256.counters.json")
+CONV_COUNTERS = {g: os.path.join(PROFILES, f"k_cycle_convergence-{g}-2048-ppc64.counters.json")
+                 for g in ("cyl", "slab")}
 KERNEL_SOURCES = ("wk_cycle_impl.h", "wk_march_impl.h", "wk_marcher.h", "wk_beam_dev.h", "wk_internal.h")
 
 
@@ -382,6 +384,8 @@ def convergence_bench(args):
             "updates_per_s": upd / (ms * 1e-3),
             "ez_rel_l2_vs_512": rel, "ez_spike_fine": peak["fine"], "ez_spike_512": peak["coarse"],
             "witness_gain": sim.witness_gain(), "counters": sim.counters_dict(),
+            "roofline": roofline(upd, ms, measured_traffic(CONV_COUNTERS[geom], upd), "k_cycle (large grid)", 1),
+            "group": sim.plan.cycle_group(args.steps),
         }
         print(f"# {geom} cycle {ms:.0f} ms", file=sys.stderr, flush=True)
         del sim
@@ -529,6 +533,14 @@ def main():
     from paper_1411_3246_amd import inputs, wake
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # a plain 1 GiB device copy: the reference that HBM counter runs
+        # scale FETCH_SIZE and WRITE_SIZE by
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        bcopy = torch.empty_like(a)
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
     if args.workload == "convergence":
         conv = convergence_bench(args)
         upd = sum(v["updates"] for v in conv.values())
@@ -568,13 +580,6 @@ def main():
     group = sim.plan.cycle_group(args.steps) if args.mode == "pipelined" else sim.plan.group
     stream = torch.cuda.current_stream()
     upd_per_step = p.updates_per_response()
-
-    if args.calibrate_copy:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
-        bcopy = torch.empty_like(a)
-        bcopy.copy_(a)
-        torch.cuda.synchronize()
-        del a, bcopy
 
     def run(n, ev=None):
         if args.mode == "pipelined":

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "wk_direct.h"
 #include "wk_internal.h"
 
 struct wk_plan {

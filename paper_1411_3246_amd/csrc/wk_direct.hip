@@ -32,6 +32,7 @@
 // LDS behind barriers.
 #include <algorithm>
 
+#include "wk_direct.h"
 #include "wk_marcher.h"
 
 namespace wk {
