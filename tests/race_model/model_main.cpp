@@ -1,0 +1,190 @@
+// CPU model run of one plasma response by the device marcher (dev::Marcher)
+// with one OS thread per GPU thread of one workgroup (see hip/hip_runtime.h
+// beside this file).  Built by tests/test_marcher_race_model.py against a
+// copy of the kernel headers, with ThreadSanitizer.
+//
+//   model <in.bin> <out.bin> <shape>
+//
+// in.bin: int32 geom, warm, n_r, n_xi, ppc, prec; int64 np; double r_max, h,
+// dxi, d_min; double x, y, px, py, d0, w [np]; nion [n_r + 1]; jb
+// [n_xi][n_r + 1].  out.bin: double fields [4][n_xi][n_r + 1]; uint64
+// counters [WK_NCOUNTERS]; uint64 workgroup barriers passed.
+#include <pthread.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wk_marcher.h"
+
+namespace {
+
+struct Input {
+    int32_t geom, warm, n_r, n_xi, ppc, prec;
+    int64_t np;
+    double r_max, h, dxi, d_min;
+    std::vector<double> x, y, px, py, d0, w, nion, jb;
+};
+
+bool read_input(const char* path, Input& in)
+{
+    FILE* f = fopen(path, "rb");
+    if (!f) return false;
+    int32_t hdr[6];
+    bool ok = fread(hdr, 4, 6, f) == 6 && fread(&in.np, 8, 1, f) == 1;
+    double c[4];
+    ok = ok && fread(c, 8, 4, f) == 4;
+    if (!ok) { fclose(f); return false; }
+    in.geom = hdr[0]; in.warm = hdr[1]; in.n_r = hdr[2]; in.n_xi = hdr[3]; in.ppc = hdr[4]; in.prec = hdr[5];
+    in.r_max = c[0]; in.h = c[1]; in.dxi = c[2]; in.d_min = c[3];
+    auto rd = [&](std::vector<double>& v, size_t n) { v.resize(n); return fread(v.data(), 8, n, f) == n; };
+    const size_t np = (size_t)in.np, N1 = (size_t)in.n_r + 1;
+    ok = rd(in.x, np) && rd(in.y, np) && rd(in.px, np) && rd(in.py, np) && rd(in.d0, np) && rd(in.w, np) &&
+         rd(in.nion, N1) && rd(in.jb, (size_t)in.n_xi * N1);
+    fclose(f);
+    return ok;
+}
+
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
+struct Run {
+    static wk::MarchDesc* desc;
+    static double* smem;
+    static void* pconst;
+    static void* body(void* arg)
+    {
+        const long tid = (long)arg;
+        threadIdx.x = (unsigned)tid;
+        blockDim.x = T;
+        wk::dev::Marcher<R, GEOM, WARM, T, K, RES, BIG> m(*desc, smem, pconst);
+        m.run();
+        return nullptr;
+    }
+    static int go(const Input& in, std::vector<double>& fields_out, unsigned long long* counters)
+    {
+        if ((in.geom == WK_CYL) != (GEOM == WK_CYL) || (in.warm != 0) != WARM) return 2;
+        if ((in.prec == WK_FP64) != (sizeof(R) == 8)) return 2;
+        const int N1 = in.n_r + 1, st = wk::lds_stride(N1);
+        const size_t np = (size_t)in.np;
+        std::vector<double> x = in.x, y = in.y, px = in.px, py = in.py;
+        std::vector<R> d0(np), w(np);
+        for (size_t i = 0; i < np; ++i) {
+            d0[i] = (R)in.d0[i];
+            w[i] = (R)in.w[i];
+        }
+        std::vector<R> fields((size_t)4 * in.n_xi * N1, (R)0);
+        std::vector<double> lds((size_t)wk::NUM_ROWS * st + 2 * (size_t)T * K + 64, 0.0);
+        std::vector<double> grow(BIG ? (size_t)wk::BIG_ROWS * st : 1, 0.0);
+        wk::MarchDesc d;
+        memset(&d, 0, sizeof(d));
+        d.geom = in.geom;
+        d.warm = in.warm;
+        d.n_r = in.n_r;
+        d.n_xi = in.n_xi;
+        d.np = in.np;
+        d.r_max = in.r_max;
+        d.h = in.h;
+        d.dxi = in.dxi;
+        d.d_min = in.d_min;
+        d.x = x.data();
+        d.y = y.data();
+        d.px = px.data();
+        d.py = py.data();
+        d.d0 = d0.data();
+        d.w = w.data();
+        d.nion = in.nion.data();
+        d.jb = in.jb.data();
+        d.fields = fields.data();
+        d.counters = counters;
+        d.grow = BIG ? grow.data() : nullptr;
+        d.ppc = in.ppc;
+        d.group = 1;
+        desc = &d;
+        smem = lds.data();
+        pconst = BIG ? nullptr : (void*)(lds.data() + (size_t)wk::NUM_ROWS * st);
+        wk_model::World world;
+        world.block.init(T);
+        for (int i = 0; i < T / 64; ++i) world.wave[i].init(64);
+        wk_model::world = &world;
+        std::vector<pthread_t> th(T);
+        pthread_attr_t attr;
+        pthread_attr_init(&attr);
+        pthread_attr_setstacksize(&attr, 1 << 20);
+        for (long t = 0; t < T; ++t)
+            if (pthread_create(&th[t], &attr, body, (void*)t) != 0) {
+                fprintf(stderr, "pthread_create failed at %ld\n", t);
+                return 3;
+            }
+        for (int t = 0; t < T; ++t) pthread_join(th[t], nullptr);
+        fields_out.assign(fields.begin(), fields.end());
+        counters[WK_NCOUNTERS] = world.barriers;
+        return 0;
+    }
+};
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
+wk::MarchDesc* Run<R, GEOM, WARM, T, K, RES, BIG>::desc = nullptr;
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
+double* Run<R, GEOM, WARM, T, K, RES, BIG>::smem = nullptr;
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG>
+void* Run<R, GEOM, WARM, T, K, RES, BIG>::pconst = nullptr;
+
+typedef int (*RunFn)(const Input&, std::vector<double>&, unsigned long long*);
+struct Entry {
+    const char* name;
+    RunFn fn;
+};
+
+#define WK_RUN(R, G, W, T, K, RES, BIG) Run<R, G, W, T, K, RES, BIG>::go
+const Entry kEntries[] = {
+    // 256 threads with one resident particle per thread (32 cells x 8 per
+    // cell, warm cylindrical): the configuration in which fields once
+    // differed from run to run
+    {"f64-cyl-warm-256x4-res", WK_RUN(double, WK_CYL, true, 256, 4, true, false)},
+    {"f64-cyl-cold-256x4-res", WK_RUN(double, WK_CYL, false, 256, 4, true, false)},
+    {"f64-slab-warm-256x4-res", WK_RUN(double, WK_SLAB, true, 256, 4, true, false)},
+    {"f64-slab-cold-256x4-res", WK_RUN(double, WK_SLAB, false, 256, 4, true, false)},
+    {"f64-cyl-warm-256x4-stream", WK_RUN(double, WK_CYL, true, 256, 4, false, false)},
+    {"f64-cyl-warm-512x4-res", WK_RUN(double, WK_CYL, true, 512, 4, true, false)},
+    {"f64-cyl-warm-512x16-res", WK_RUN(double, WK_CYL, true, 512, 16, true, false)},
+    {"f64-cyl-warm-1024x8-res", WK_RUN(double, WK_CYL, true, 1024, 8, true, false)},
+    {"f64-cyl-warm-512x8-big-stream", WK_RUN(double, WK_CYL, true, 512, 8, false, true)},
+    {"f32-cyl-warm-512x8-res", WK_RUN(float, WK_CYL, true, 512, 8, true, false)},
+    {"f32-cyl-warm-512x8-big-res", WK_RUN(float, WK_CYL, true, 512, 8, true, true)},
+};
+
+}  // namespace
+
+int main(int argc, char** argv)
+{
+    if (argc == 2 && std::string(argv[1]) == "--list") {
+        for (const Entry& e : kEntries) printf("%s\n", e.name);
+        return 0;
+    }
+    if (argc != 4) {
+        fprintf(stderr, "usage: model <in.bin> <out.bin> <shape> | --list\n");
+        return 1;
+    }
+    Input in;
+    if (!read_input(argv[1], in)) {
+        fprintf(stderr, "cannot read %s\n", argv[1]);
+        return 1;
+    }
+    for (const Entry& e : kEntries) {
+        if (std::string(e.name) != argv[3]) continue;
+        std::vector<double> fields;
+        unsigned long long counters[WK_NCOUNTERS + 1] = {0};
+        const int rc = e.fn(in, fields, counters);
+        if (rc != 0) {
+            fprintf(stderr, "shape %s does not fit the input (rc %d)\n", e.name, rc);
+            return rc;
+        }
+        FILE* f = fopen(argv[2], "wb");
+        if (!f) return 1;
+        fwrite(fields.data(), 8, fields.size(), f);
+        fwrite(counters, 8, WK_NCOUNTERS + 1, f);
+        fclose(f);
+        return 0;
+    }
+    fprintf(stderr, "unknown shape %s\n", argv[3]);
+    return 1;
+}

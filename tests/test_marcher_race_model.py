@@ -1,0 +1,161 @@
+"""The marcher's barrier schedule, checked on the CPU.
+
+The device marcher (dev::Marcher in csrc/wk_marcher.h, the code every march,
+batch and cycle kernel runs) is compiled for the host against a model of
+the device environment (tests/race_model/hip/hip_runtime.h): one OS thread
+per GPU thread of one workgroup, every workgroup barrier a thread barrier,
+every cross-lane operation (DPP row shifts and broadcasts, ds_bpermute) a
+barrier of the 64 threads of its wavefront that exchanges their values, LDS
+and global memory plain shared memory.  Built with ThreadSanitizer, a pair of
+accesses to one address by two threads that no barrier orders, one of them a
+write, is reported as a race; a barrier that not every thread reaches leaves the run
+hanging, which the time limit reports.
+
+The kernel headers are copied unchanged except for their three inline-asm
+statements (the vmcnt and lgkmcnt waits and the compiler fence of the LDS
+barrier), which become calls into the model; the copy is checked to contain
+no other asm.  Each shape runs one response and its fields are compared with
+the oracle's (FP64 within 1e-10 of each field's scale, mixed precision
+||dE_z|| / ||E_z|| <= 1e-3), which shows that the model executes the march
+faithfully, cross-lane operations included.
+
+What the model does not see: ordering of global memory by the LDS-only
+barrier (on the GPU it orders LDS accesses only; the marcher keeps its
+cross-thread data in LDS except for the large-grid rows, which use the
+waiting barrier) and the exchanges between the workgroups of a group.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1411_3246_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_1411_3246_amd", "csrc")
+MODEL = os.path.join(HERE, "race_model")
+
+ASM = {
+    'asm volatile("s_waitcnt vmcnt(0)" ::: "memory");': "wk_model::wait_vm();",
+    'asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");': "wk_model::wait_lgkm();",
+    'asm volatile("" ::: "memory");': "wk_model::compiler_fence();",
+}
+
+
+def _build(d, mutate=None):
+    """Copy the kernel headers into d (asm statements modelled, `mutate`
+    applied to the marcher) and build the model there."""
+    os.makedirs(d / "pkg" / "csrc")
+    os.makedirs(d / "include")
+    shutil.copy(os.path.join(ROOT, "include", "wake.h"), d / "include" / "wake.h")
+    for name in ("wk_marcher.h", "wk_internal.h"):
+        with open(os.path.join(CSRC, name)) as f:
+            src = f.read()
+        for old, new in ASM.items():
+            src = src.replace(old, new)
+        assert not re.search(r"\basm\b\s*(volatile)?\s*\(", src), f"unmodelled inline asm in {name}"
+        if mutate and name == "wk_marcher.h":
+            src = mutate(src)
+        with open(d / "pkg" / "csrc" / name, "w") as f:
+            f.write(src)
+    exe = str(d / "model")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-pthread", "-I", MODEL,
+           "-I", str(d / "pkg" / "csrc"), os.path.join(MODEL, "model_main.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
+@pytest.fixture(scope="module")
+def model(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    d = tmp_path_factory.mktemp("race_model")
+    return _build(d), d
+
+
+CASES = [
+    # (shape, problem)
+    ("f64-cyl-warm-256x4-res", dict(n_r=32, ppc=8, u_th=0.02)),
+    ("f64-cyl-cold-256x4-res", dict(n_r=32, ppc=8, u_th=0.0)),
+    ("f64-slab-warm-256x4-res", dict(n_r=32, ppc=8, u_th=0.02, geom="slab", r_max=8.0)),
+    ("f64-slab-cold-256x4-res", dict(n_r=32, ppc=8, u_th=0.0, geom="slab", r_max=8.0)),
+    ("f64-cyl-warm-256x4-res", dict(n_r=64, ppc=16, u_th=0.02)),            # 4 per thread
+    ("f64-cyl-warm-256x4-stream", dict(n_r=48, ppc=24, u_th=0.02)),         # two tiles
+    ("f64-cyl-warm-512x4-res", dict(n_r=37, ppc=16, u_th=0.02)),            # ragged
+    ("f64-cyl-warm-512x16-res", dict(n_r=64, ppc=64, u_th=0.02)),
+    ("f64-cyl-warm-1024x8-res", dict(n_r=64, ppc=16, u_th=0.02)),
+    ("f64-cyl-warm-512x8-big-stream", dict(n_r=40, ppc=16, u_th=0.02)),
+    ("f32-cyl-warm-512x8-res", dict(n_r=64, ppc=32, u_th=0.02, prec="mixed")),
+    ("f32-cyl-warm-512x8-big-res", dict(n_r=64, ppc=16, u_th=0.02, prec="mixed")),
+]
+
+
+def _write_input(path, p, st, jb):
+    hdr = np.array([0 if p.geom == "cyl" else 1, 1 if p.u_th > 0 else 0, p.n_r, p.n_xi, p.ppc,
+                    0 if p.prec == "fp64" else 1], dtype=np.int32)
+    with open(path, "wb") as f:
+        f.write(hdr.tobytes())
+        f.write(np.array([len(st["x"])], dtype=np.int64).tobytes())
+        f.write(np.array([p.r_max, p.r_max / p.n_r, p.dxi, p.d_min], dtype=np.float64).tobytes())
+        for k in ("x", "y", "px", "py", "d0", "w", "nion"):
+            f.write(np.ascontiguousarray(st[k], dtype=np.float64).tobytes())
+        f.write(np.ascontiguousarray(jb, dtype=np.float64).tobytes())
+
+
+@pytest.mark.parametrize("shape,kw", CASES, ids=[f"{s}-{k['n_r']}x{k['ppc']}" for s, k in CASES])
+def test_barrier_schedule_race_free(model, oracle_lib, shape, kw):
+    exe, d = model
+    r, p, fout, ref = _run(exe, d, oracle_lib, shape, kw)
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-6000:]
+    assert r.returncode == 0, r.stderr[-2000:]
+    N1 = p.n_r + 1
+    raw = np.fromfile(fout, dtype=np.float64, count=4 * p.n_xi * N1).reshape(4, p.n_xi, N1)
+    cnt = np.fromfile(fout, dtype=np.uint64, offset=8 * 4 * p.n_xi * N1)
+    assert cnt[-1] > 10 * p.n_xi                     # workgroup barriers passed
+    f0 = ref["fields"]
+    if p.prec == "fp64":
+        for i in range(4):
+            scale = np.max(np.abs(f0[i]))
+            assert np.max(np.abs(raw[i] - f0[i])) <= 1e-10 * scale, (i, np.max(np.abs(raw[i] - f0[i])) / scale)
+        assert int(cnt[0]) == int(ref["counters"][0]) and int(cnt[1]) == int(ref["counters"][1])
+    else:
+        assert np.linalg.norm(raw[1] - f0[1]) <= 1e-3 * np.linalg.norm(f0[1])
+
+
+def test_model_reports_a_missing_barrier(tmp_path, oracle_lib):
+    """The check has teeth: with the barrier between the stage-1 psi solve
+    and the moment deposit (which gathers psi at the particles) taken out of
+    a copy of the marcher, the model reports a race."""
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    cut = "            solve_psi(psi2);\n            sync();\n"
+
+    def mutate(src):
+        assert cut in src
+        return src.replace(cut, "            solve_psi(psi2);\n", 1)
+    exe = _build(tmp_path, mutate)
+    r, _, _, _ = _run(exe, tmp_path, oracle_lib, "f64-cyl-warm-256x4-res", dict(n_r=32, ppc=8, u_th=0.02))
+    assert "ThreadSanitizer: data race" in r.stderr, r.stderr[-2000:]
+    assert "solve_psi" in r.stderr or "dep_moments" in r.stderr
+
+
+def _run(exe, d, O, shape, kw):
+    base = dict(n_xi=40, n_d=1.0, n_beam=0, prec="fp64")
+    base.update(kw)
+    full = inputs.facet_two_bunch(**base, name=f"model-{shape}")
+    # the first 16 slices of the 40-slice window: through the drive bunch
+    p = full.replace(n_xi=16, xi_max=full.xi_min + 16 * full.dxi)
+    st = O.load_plasma(p, inputs.plasma_draws(p))
+    jb = O.beam_current_analytic(p)
+    ref = O.response(p.replace(prec="fp64"), inputs.plasma_draws(p))
+    fin = str(d / f"{shape}-{p.n_r}.in")
+    fout = str(d / f"{shape}-{p.n_r}.out")
+    _write_input(fin, p, st, jb)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0")
+    r = subprocess.run([exe, fin, fout, shape], capture_output=True, text=True, timeout=600, env=env)
+    return r, p, fout, ref
