@@ -114,6 +114,9 @@ inline int update_dpp(int old, int src, int ctrl, int row_mask, int, bool)
 
 inline int ds_bpermute(int addr, int src) { return (int)lane_of((int64_t)src, (addr >> 2) & 63); }
 
+// Dynamic LDS of the modelled workgroup (kernels' extern __shared__ arrays).
+inline double* dynamic_lds = nullptr;
+
 inline void wait_vm() {}
 inline void wait_lgkm() {}
 inline void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
@@ -128,6 +131,26 @@ inline unsigned long long clock64()
 }  // namespace wk_model
 
 inline void __syncthreads() { wk_model::block_barrier(); }
+inline double __shfl_xor(double v, int mask, int = 64)
+{
+    int64_t u;
+    memcpy(&u, &v, 8);
+    u = wk_model::lane_of(u, (int)(threadIdx.x & 63) ^ mask);
+    double r;
+    memcpy(&r, &u, 8);
+    return r;
+}
+
+// Host launch interface seen by kernel sources (the model calls the device
+// code directly and never launches).
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+inline hipError_t hipFuncSetAttribute(const void*, int, int) { return hipSuccess; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+#define hipLaunchKernelGGL(...) ((void)0)
 #define __builtin_amdgcn_s_barrier() wk_model::block_barrier()
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) wk_model::update_dpp(old, src, ctrl, rm, bm, bc)
 #define __builtin_amdgcn_ds_bpermute(addr, src) wk_model::ds_bpermute(addr, src)

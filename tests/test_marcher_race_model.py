@@ -52,22 +52,27 @@ def _build(d, mutate=None):
     os.makedirs(d / "pkg" / "csrc")
     os.makedirs(d / "include")
     shutil.copy(os.path.join(ROOT, "include", "wake.h"), d / "include" / "wake.h")
-    for name in ("wk_marcher.h", "wk_internal.h"):
+    for name in ("wk_marcher.h", "wk_internal.h", "wk_direct.h", "wk_direct.hip"):
         with open(os.path.join(CSRC, name)) as f:
             src = f.read()
         for old, new in ASM.items():
             src = src.replace(old, new)
         assert not re.search(r"\basm\b\s*(volatile)?\s*\(", src), f"unmodelled inline asm in {name}"
+        # a kernel's dynamic LDS is the modelled workgroup's buffer
+        src = src.replace("extern __shared__ double smem[];", "double* smem = wk_model::dynamic_lds;")
         if mutate and name == "wk_marcher.h":
             src = mutate(src)
         with open(d / "pkg" / "csrc" / name, "w") as f:
             f.write(src)
-    exe = str(d / "model")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-pthread", "-I", MODEL,
-           "-I", str(d / "pkg" / "csrc"), os.path.join(MODEL, "model_main.cpp"), "-o", exe]
-    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
-    assert r.returncode == 0, r.stderr[-4000:]
-    return exe
+    exes = []
+    for main in ("model_main.cpp", "model_direct_main.cpp"):
+        exe = str(d / main.replace(".cpp", ""))
+        cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-pthread", "-I", MODEL,
+               "-I", str(d / "pkg" / "csrc"), os.path.join(MODEL, main), "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+        assert r.returncode == 0, r.stderr[-4000:]
+        exes.append(exe)
+    return exes
 
 
 @pytest.fixture(scope="module")
@@ -109,7 +114,7 @@ def _write_input(path, p, st, jb):
 
 @pytest.mark.parametrize("shape,kw", CASES, ids=[f"{s}-{k['n_r']}x{k['ppc']}" for s, k in CASES])
 def test_barrier_schedule_race_free(model, oracle_lib, shape, kw):
-    exe, d = model
+    (exe, _), d = model
     r, p, fout, ref = _run(exe, d, oracle_lib, shape, kw)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-6000:]
     assert r.returncode == 0, r.stderr[-2000:]
@@ -138,7 +143,7 @@ def test_model_reports_a_missing_barrier(tmp_path, oracle_lib):
     def mutate(src):
         assert cut in src
         return src.replace(cut, "            solve_psi(psi2);\n", 1)
-    exe = _build(tmp_path, mutate)
+    exe, _ = _build(tmp_path, mutate)
     r, _, _, _ = _run(exe, tmp_path, oracle_lib, "f64-cyl-warm-256x4-res", dict(n_r=32, ppc=8, u_th=0.02))
     assert "ThreadSanitizer: data race" in r.stderr, r.stderr[-2000:]
     assert "solve_psi" in r.stderr or "dep_moments" in r.stderr
@@ -148,8 +153,8 @@ def _run(exe, d, O, shape, kw):
     base = dict(n_xi=40, n_d=1.0, n_beam=0, prec="fp64")
     base.update(kw)
     full = inputs.facet_two_bunch(**base, name=f"model-{shape}")
-    # the first 16 slices of the 40-slice window: through the drive bunch
-    p = full.replace(n_xi=16, xi_max=full.xi_min + 16 * full.dxi)
+    # the first 12 slices of the 40-slice window: into the drive bunch
+    p = full.replace(n_xi=12, xi_max=full.xi_min + 12 * full.dxi)
     st = O.load_plasma(p, inputs.plasma_draws(p))
     jb = O.beam_current_analytic(p)
     ref = O.response(p.replace(prec="fp64"), inputs.plasma_draws(p))
@@ -159,3 +164,39 @@ def _run(exe, d, O, shape, kw):
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0")
     r = subprocess.run([exe, fin, fout, shape], capture_output=True, text=True, timeout=600, env=env)
     return r, p, fout, ref
+
+
+@pytest.mark.parametrize("kw", [dict(u_th=0.02, n_d=0.3), dict(u_th=0.02, n_d=0.3, geom="slab", r_max=8.0)],
+                         ids=["warm-cyl", "warm-slab"])
+def test_direct_response_race_free(model, oracle_lib, kw):
+    """The Eq. (6)-direct response (wk_direct.hip: the marcher's deposits and
+    solves, block reductions by lane shuffles, GMRES with thread 0 applying
+    the rotations) in the same model: race free, and its fields equal the
+    oracle's direct march within 1e-10 of each field's scale, with the same
+    Newton step counts."""
+    (_, exe), d = model
+    O = oracle_lib
+    full = inputs.facet_two_bunch(n_r=24, n_xi=40, ppc=2, n_beam=0, prec="fp64", name="model-direct", **kw)
+    # six slices of the 40-slice window, where the drive's head arrives
+    p = full.replace(n_xi=6, xi_min=full.xi_min + 6 * full.dxi, xi_max=full.xi_min + 12 * full.dxi)
+    st = O.load_plasma(p, inputs.plasma_draws(p))
+    jb = O.beam_current_analytic(p)
+    f0, c0, it0 = O.march_direct(p, {k: v.copy() for k, v in st.items()}, jb, tol=1e-9)
+    fin, fout = str(d / "direct.in"), str(d / "direct.out")
+    _write_input(fin, p, st, jb)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0")
+    r = subprocess.run([exe, fin, fout, "8", "1e-9"], capture_output=True, text=True, timeout=900, env=env)
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-6000:]
+    assert r.returncode == 0, r.stderr[-2000:]
+    N1 = p.n_r + 1
+    n_f = 4 * p.n_xi * N1
+    f = np.fromfile(fout, dtype=np.float64, count=n_f).reshape(4, p.n_xi, N1)
+    n_cnt = 8                                        # WK_NCOUNTERS
+    cnt = np.fromfile(fout, dtype=np.uint64, count=n_cnt, offset=8 * n_f)
+    its = np.fromfile(fout, dtype=np.int32, offset=8 * n_f + 8 * n_cnt)
+    top = np.max(np.abs(f0))
+    for i in range(4):
+        scale = np.max(np.abs(f0[i])) or top
+        assert np.max(np.abs(f[i] - f0[i])) <= 1e-10 * scale, (i, np.max(np.abs(f[i] - f0[i])) / scale)
+    assert np.array_equal(its, it0), (its, it0)
+    assert int(cnt[0]) == int(c0[0]) and int(cnt[1]) == int(c0[1])
