@@ -48,6 +48,7 @@ struct WkModelIdx {
 inline thread_local WkModelIdx threadIdx = {0, 0, 0};
 inline thread_local WkModelIdx blockIdx = {0, 0, 0};
 inline thread_local WkModelIdx blockDim = {1, 1, 1};
+inline thread_local WkModelIdx gridDim = {1, 1, 1};
 
 #define __HIP_MEMORY_SCOPE_AGENT 3
 
