@@ -66,13 +66,14 @@ def source_hash() -> str:
 def measured_traffic(path: str, updates: float):
     """HBM bytes of a launch of `updates` particle-slice updates from the
     committed counter record, or None when the kernel sources changed since
-    it was taken."""
+    it was taken, or when the record is of another launch size (another step
+    count changes the cycle's group size and so its exchange traffic)."""
     try:
         with open(path) as f:
             rec = json.load(f)
-        if source_hash() != rec.get("source_hash"):
-            return None
     except OSError:
+        return None
+    if source_hash() != rec.get("source_hash") or int(rec.get("updates", -1)) != int(updates):
         return None
     return rec["bytes_per_update"] * updates
 
@@ -384,7 +385,8 @@ def convergence_bench(args):
             "updates_per_s": upd / (ms * 1e-3),
             "ez_rel_l2_vs_512": rel, "ez_spike_fine": peak["fine"], "ez_spike_512": peak["coarse"],
             "witness_gain": sim.witness_gain(), "counters": sim.counters_dict(),
-            "roofline": roofline(upd, ms, measured_traffic(CONV_COUNTERS[geom], upd), "k_cycle (large grid)", 1),
+            "roofline": roofline(upd, ms, measured_traffic(CONV_COUNTERS[geom], upd),
+                                 "k_cycle (large grid)", 1),
             "group": sim.plan.cycle_group(args.steps),
         }
         print(f"# {geom} cycle {ms:.0f} ms", file=sys.stderr, flush=True)
