@@ -97,11 +97,12 @@ struct CycleHooks : M::NoRecord {
     const unsigned* in_order;
     unsigned* out_start;
     unsigned* out_order;
+    unsigned pend;         // movers of the last old bin, written at [pos, pos + pend) of the new order
     unsigned long long out_push, out_dep, bad_bin;
 
     __device__ __forceinline__ CycleHooks(const CycleDesc& cd, int resp, int rank, int* wt, double* ring_rows,
                                           int stride)
-        : c(cd), n(resp), g(rank), next_bin(0), wtot(wt), ring(ring_rows), st(stride), seen(0), pos(0),
+        : c(cd), n(resp), g(rank), next_bin(0), wtot(wt), ring(ring_rows), st(stride), seen(0), pos(0), pend(0),
           out_push(0), out_dep(0), bad_bin(0)
     {
         const int G = c.base.group;
@@ -136,64 +137,109 @@ struct CycleHooks : M::NoRecord {
         __syncthreads();
     }
 
-    // New bin b of the pushed beam: the particles of old bin b-1 that left it,
-    // then the ones of old bin b that stayed (xi only grows, by far less than
-    // a slice per step).
-    __device__ __forceinline__ void emit_movers(int b)
-    {
-        if (threadIdx.x == 0) st_dev(out_start + b, pos);
-        if (b == 0) return;
-        const int from = b - 1;
-        pos += compact_append<T>(in_order, ld_dev(in_start + from), ld_dev(in_start + from + 1),
-                                 [&](unsigned i) { return cell_of(i) != from; }, out_order, pos, wtot);
-    }
+    // Chunks (of T particles) of a bin whose movers are kept in registers
+    // until the bin's stayers are counted; the movers of later chunks are
+    // found again.
+    static constexpr int kMvChunks = 4;
 
-    __device__ __forceinline__ void emit_stayers(int b)
-    {
-        pos += compact_append<T>(in_order, ld_dev(in_start + b), ld_dev(in_start + b + 1),
-                                 [&](unsigned i) { return cell_of(i) == b; }, out_order, pos, wtot);
-    }
-
-    // Advance (step n-1) the particles of this subset's xi bin b and count the
-    // ones outside the window; then bin b of the new order is complete.
+    // Advance (step n-1) the particles of this subset's old xi bin b, deposit
+    // their current, and write the new order.  New bin b is the particles of
+    // old bin b-1 that left it (written when that bin was processed), then the
+    // particles of old bin b that stay in it (xi only grows, by far less than a
+    // slice per step); the ones that leave old bin b are written after those
+    // and open new bin b+1.  Each particle's slot comes from wavefront ballots
+    // over the pass that pushes it, so the order is that of the old order.
     __device__ __forceinline__ void process_bin(int b)
     {
         const GridDesc& gr = c.grid;
         const int nxi = gr.n_xi;
+        const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+        constexpr int nw = T >> 6;
         if (n > 0) {
             // the last bin also waits for response n-1 to finish reading the
             // order slot that this response writes
             const unsigned need = (b == nxi - 1 && n >= 2) ? (unsigned)nxi + 1u : (unsigned)min(b + kLag, nxi);
             wait_prev(need);
-            emit_movers(b);
+            if (tid == 0) st_dev(out_start + b, pos);
+            pos += pend;
+            pend = 0;
         }
         const unsigned beg = ld_dev(in_start + b), end = ld_dev(in_start + b + 1);
         const double xi_max = gr.xi_min + nxi * gr.dxi;
-        for (unsigned q = beg + threadIdx.x; q < end; q += T) {
-            const unsigned i = ld_dev(in_order + q);
-            double x = ld_dev(B.x + i), y = ld_dev(B.y + i), xi = ld_dev(B.xi + i);
-            if (n > 0) {
-                double px = ld_dev(B.px + i), py = ld_dev(B.py + i), pz = ld_dev(B.pz + i);
-                out_push += dev::beam_push_particle<R, true>(gr, prev, x, y, xi, px, py, pz, 1, c.dt);
-                st_dev(B.x + i, x);
-                st_dev(B.y + i, y);
-                st_dev(B.xi + i, xi);
-                st_dev(B.px + i, px);
-                st_dev(B.py + i, py);
-                st_dev(B.pz + i, pz);
-                const int kk = dev::beam_xi_bin(gr, xi);
-                if (kk != nxi && kk != b && kk != b + 1) ++bad_bin;   // moved by more than a slice
+        unsigned mv_idx[kMvChunks], mv_rank[kMvChunks];
+        unsigned n_stay = 0, n_move = 0;
+        unsigned n_move_rec = 0;   // movers of the chunks kept in registers
+        int ci = 0;
+        for (unsigned base = beg; base < end; base += T, ++ci) {
+            if (ci == kMvChunks) n_move_rec = n_move;
+            const unsigned q = base + tid;
+            unsigned i = 0;
+            bool stay = false, move = false;
+            if (q < end) {
+                i = ld_dev(in_order + q);
+                double x = ld_dev(B.x + i), y = ld_dev(B.y + i), xi = ld_dev(B.xi + i);
+                if (n > 0) {
+                    double px = ld_dev(B.px + i), py = ld_dev(B.py + i), pz = ld_dev(B.pz + i);
+                    out_push += dev::beam_push_particle<R, true>(gr, prev, x, y, xi, px, py, pz, 1, c.dt);
+                    st_dev(B.x + i, x);
+                    st_dev(B.y + i, y);
+                    st_dev(B.xi + i, xi);
+                    st_dev(B.px + i, px);
+                    st_dev(B.py + i, py);
+                    st_dev(B.pz + i, pz);
+                    const int kk = dev::beam_xi_bin(gr, xi);
+                    if (kk != nxi && kk != b && kk != b + 1) ++bad_bin;   // moved by more than a slice
+                    stay = kk == b;
+                    move = !stay;
+                }
+                const double r = dev::beam_radius(gr, x, y);
+                if (r > gr.r_max || xi < gr.xi_min || xi >= xi_max) ++out_dep;
+                else if (ring) ring_deposit(r, xi, B.w[i], b);
             }
-            const double r = dev::beam_radius(gr, x, y);
-            if (r > gr.r_max || xi < gr.xi_min || xi >= xi_max) {
-                ++out_dep;
-                continue;
+            if (n == 0) continue;
+            const unsigned long long ms = __ballot(stay), mm = __ballot(move);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            if (lane == 0) {
+                wtot[wid] = __popcll(ms);
+                wtot[nw + wid] = __popcll(mm);
             }
-            if (ring) ring_deposit(r, xi, B.w[i], b);
+            __syncthreads();
+            unsigned off_s = 0, off_m = 0, ch_s = 0, ch_m = 0;
+#pragma unroll
+            for (int w = 0; w < nw; ++w) {
+                const unsigned cs = (unsigned)wtot[w], cm = (unsigned)wtot[nw + w];
+                if (w < wid) {
+                    off_s += cs;
+                    off_m += cm;
+                }
+                ch_s += cs;
+                ch_m += cm;
+            }
+            if (stay) st_dev(out_order + pos + n_stay + off_s + __popcll(ms & below), i);
+#pragma unroll
+            for (int r = 0; r < kMvChunks; ++r)
+                if (r == ci) {
+                    mv_idx[r] = move ? i : ~0u;
+                    mv_rank[r] = n_move + off_m + __popcll(mm & below);
+                }
+            n_stay += ch_s;
+            n_move += ch_m;
+            __syncthreads();   // wtot is reused by the next chunk
         }
-        dev::wait_vm();
-        __syncthreads();
-        if (n > 0) emit_stayers(b);
+        if (n > 0) {
+            // the movers after the stayers: those of the first chunks from
+            // registers, those of later chunks found again (their new xi was
+            // stored by this same thread)
+            const unsigned pm = pos + n_stay;
+#pragma unroll
+            for (int r = 0; r < kMvChunks; ++r)
+                if (r < ci && mv_idx[r] != ~0u) st_dev(out_order + pm + mv_rank[r], mv_idx[r]);
+            if (ci > kMvChunks)
+                compact_append<T>(in_order, beg + (unsigned)kMvChunks * T, end,
+                                  [&](unsigned i) { return cell_of(i) != b; }, out_order, pm + n_move_rec, wtot);
+            pos = pm;
+            pend = n_move;
+        }
         dev::wait_vm();
         __syncthreads();
     }
@@ -299,7 +345,11 @@ struct CycleHooks : M::NoRecord {
         }
         dev::wait_vm();
         __syncthreads();
-        emit_movers(nxi);
+        // the new outside bin: the movers of the last old bin (written when it
+        // was processed), then the particles that were outside already
+        if (threadIdx.x == 0) st_dev(out_start + nxi, pos);
+        pos += pend;
+        pend = 0;
         pos += compact_append<T>(in_order, beg, end, [&](unsigned) { return true; }, out_order, pos, wtot);
         if (threadIdx.x == 0) {
             st_dev(out_start + nxi + 1, pos);
@@ -358,7 +408,7 @@ __global__ __launch_bounds__(T, WPS) void k_cycle(CycleDesc c)
 {
     extern __shared__ double smem[];
     __shared__ int s_ticket;
-    __shared__ int wtot[T / 64];
+    __shared__ int wtot[2 * (T / 64)];
     using M = dev::Marcher<R, GEOM, WARM, T, K, RES, BIG>;
     const int G = c.base.group;
     const int N1 = c.base.n_r + 1;
