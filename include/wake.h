@@ -198,7 +198,9 @@ wk_status wk_beam_current_analytic(const wk_plan* plan, double* d_jb, void* stre
 /* Beam current, macroparticles: J_bz = -sum W hat_j(r) hat_k(xi) / (V_j dxi) with
  * v_z = c (Section II A: the total current includes the beam current).
  * Uses the workspace for the xi binning of the beam; counts particles
- * outside the window. */
+ * outside the window.  The result depends on the beam alone: each xi cell's
+ * particles are summed in index order, so repeated calls give the same rows
+ * bit for bit. */
 wk_status wk_beam_current(const wk_plan* plan, const wk_beam_bufs* beam, double* d_jb,
                           void* d_workspace, uint64_t* d_counters, void* stream);
 

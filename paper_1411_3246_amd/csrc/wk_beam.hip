@@ -272,6 +272,89 @@ __global__ void k_beam_scatter(GridDesc g, int64_t n, wk_beam_bufs b, unsigned i
     order[pos] = (unsigned int)i;
 }
 
+// The particle indices of each xi cell in ascending order (one workgroup per
+// cell): the scatter's atomic counter hands out the slots of a cell in an
+// order that depends on scheduling, and the sort makes the order, and so the
+// summation order of the rows, a function of the beam alone.  Runs of up to
+// kSortCap indices are sorted in LDS (bitonic network); longer cells then
+// merge their runs pairwise through `tmp` (each output element placed by a
+// binary search along the merge path).
+constexpr int kSortT = 1024;
+constexpr int kSortCap = 8192;
+
+__device__ __forceinline__ void bitonic_lds(unsigned* v, int n2)
+{
+    for (int k = 2; k <= n2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const unsigned x = v[i], y = v[l];
+                    if ((x > y) == up) {
+                        v[i] = y;
+                        v[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
+__global__ __launch_bounds__(kSortT) void k_bin_sort(const unsigned int* start, unsigned int* order,
+                                                     unsigned int* tmp)
+{
+    __shared__ unsigned v[kSortCap];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const unsigned beg = start[c], n = start[c + 1] - beg;
+    if (n <= 1) return;
+    unsigned* src = order + beg;
+    unsigned* dst = tmp + beg;
+    for (unsigned r0 = 0; r0 < n; r0 += kSortCap) {
+        const unsigned m = min(n - r0, (unsigned)kSortCap);
+        int m2 = 1;
+        while ((unsigned)m2 < m) m2 <<= 1;
+        for (int i = tid; i < m2; i += kSortT) v[i] = (unsigned)i < m ? src[r0 + i] : 0xffffffffu;
+        __syncthreads();
+        bitonic_lds(v, m2);
+        for (unsigned i = tid; i < m; i += kSortT) src[r0 + i] = v[i];
+        __syncthreads();
+    }
+    for (unsigned w = kSortCap; w < n; w <<= 1) {
+        for (unsigned t = tid; t < n; t += kSortT) {
+            const unsigned s0 = (t / (2 * w)) * (2 * w);
+            const unsigned a1 = min(s0 + w, n), b1 = min(s0 + 2 * w, n);
+            const unsigned na = a1 - s0, nb = b1 - a1, o = t - s0;
+            const unsigned* A = src + s0;
+            const unsigned* B = src + a1;
+            // elements of A among the first o outputs (indices are distinct)
+            unsigned lo = o > nb ? o - nb : 0, hi = min(o, na);
+            while (lo < hi) {
+                const unsigned mid = (lo + hi) >> 1;
+                if (A[mid] < B[o - 1 - mid]) lo = mid + 1;
+                else hi = mid;
+            }
+            const unsigned ia = lo, ib = o - lo;
+            dst[t] = (ia < na && (ib >= nb || A[ia] < B[ib])) ? A[ia] : B[ib];
+        }
+        __syncthreads();
+        unsigned* t2 = src;
+        src = dst;
+        dst = t2;
+    }
+    if (src != order + beg) {
+        for (unsigned t = tid; t < n; t += kSortT) order[beg + t] = src[t];
+    }
+}
+
+// Row k of J_bz from the particles of cells k-1 (weight tk towards slice k)
+// and k (weight 1 - tk), in their sorted order.  Each node's sum is formed by
+// one thread, adding the particles' contributions in list order, so that the
+// row does not depend on scheduling: chunks of kRowChunk particles are
+// staged in LDS (hat cell and the two node contributions) and every thread
+// walks the chunk for the nodes it owns.
+constexpr int kRowChunk = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_beam_rows(GridDesc g, wk_beam_bufs b,
                                                       const unsigned int* start,
                                                       const unsigned int* order, double* jb)
@@ -279,29 +362,48 @@ __global__ __launch_bounds__(kBlock) void k_beam_rows(GridDesc g, wk_beam_bufs b
     extern __shared__ double acc[];
     const int k = blockIdx.x;
     const int N1 = g.n_r + 1;
+    double* clo = acc + ((N1 + 1) & ~1);
+    double* chi = clo + kRowChunk;
+    int* cj = (int*)(chi + kRowChunk);
     for (int j = threadIdx.x; j < N1; j += blockDim.x) acc[j] = 0.0;
-    __syncthreads();
-    // cells k-1 (weight tk towards slice k) and k (weight 1 - tk)
     const int c0 = k > 0 ? k - 1 : 0;
-    const unsigned int beg = start[c0], end = start[k + 1];
-    for (unsigned int q = beg + threadIdx.x; q < end; q += blockDim.x) {
-        const unsigned int i = order[q];
-        const double x = b.d_x[i], y = b.d_y[i];
-        const double r = g.geom == WK_CYL ? sqrt(x * x + y * y) : fabs(x);
-        int j;
-        double tr;
-        hat(g, r, j, tr);
-        const double u = (b.d_xi[i] - g.xi_min) / g.dxi;
-        int kk = (int)floor(u);
-        if (kk > g.n_xi - 1) kk = g.n_xi - 1;
-        const double tk = u - kk;
-        double wk;
-        if (kk == k) wk = 1.0 - tk;
-        else if (kk == k - 1) wk = tk;
-        else continue;
-        const double wb = b.d_w[i];
-        atomicAdd(acc + j, wb * (1.0 - tr) * wk);
-        atomicAdd(acc + j + 1, wb * tr * wk);
+    const unsigned beg = start[c0], end = start[k + 1];
+    for (unsigned base = beg; base < end; base += kRowChunk) {
+        const unsigned m = min(end - base, (unsigned)kRowChunk);
+        __syncthreads();
+        for (unsigned p = threadIdx.x; p < m; p += blockDim.x) {
+            const unsigned i = order[base + p];
+            const double x = b.d_x[i], y = b.d_y[i];
+            const double r = g.geom == WK_CYL ? sqrt(x * x + y * y) : fabs(x);
+            int j;
+            double tr;
+            hat(g, r, j, tr);
+            const double u = (b.d_xi[i] - g.xi_min) / g.dxi;
+            int kk = (int)floor(u);
+            if (kk > g.n_xi - 1) kk = g.n_xi - 1;
+            const double tk = u - kk;
+            double wk;
+            if (kk == k) wk = 1.0 - tk;
+            else if (kk == k - 1) wk = tk;
+            else {
+                cj[p] = -2;
+                continue;
+            }
+            const double wb = b.d_w[i];
+            cj[p] = j;
+            clo[p] = wb * (1.0 - tr) * wk;
+            chi[p] = wb * tr * wk;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < N1; j += blockDim.x) {
+            double sum = acc[j];
+            for (unsigned p = 0; p < m; ++p) {
+                const int q = cj[p];
+                if (q == j) sum += clo[p];
+                else if (q + 1 == j) sum += chi[p];
+            }
+            acc[j] = sum;
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < N1; j += blockDim.x)
@@ -452,9 +554,9 @@ inline unsigned int nblocks(int64_t n, int b) { return (unsigned int)((n + b - 1
 
 size_t beam_ws_bytes(int n_xi, int64_t n_beam)
 {
+    const size_t order = align256(sizeof(unsigned int) * (size_t)(n_beam > 0 ? n_beam : 1));
     return align256(sizeof(unsigned int) * (size_t)n_xi) + align256(sizeof(unsigned int) * (size_t)(n_xi + 1)) +
-           align256(sizeof(unsigned int) * (size_t)n_xi) + align256(sizeof(unsigned int) * (size_t)(n_beam > 0 ? n_beam : 1)) +
-           align256(sizeof(double) * 2 * kGainBlocks);
+           align256(sizeof(unsigned int) * (size_t)n_xi) + 2 * order + align256(sizeof(double) * 2 * kGainBlocks);
 }
 
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s)
@@ -531,6 +633,8 @@ hipError_t launch_beam_current(const GridDesc& g, int64_t n_beam, const wk_beam_
     unsigned int* fill = (unsigned int*)p;
     p += align256(sizeof(unsigned int) * (size_t)g.n_xi);
     unsigned int* order = (unsigned int*)p;
+    p += align256(sizeof(unsigned int) * (size_t)(n_beam > 0 ? n_beam : 1));
+    unsigned int* sort_tmp = (unsigned int*)p;
     hipError_t e = launch_zero_u32(count, g.n_xi, s);
     if (e != hipSuccess) return e;
     if (n_beam > 0) {
@@ -542,7 +646,9 @@ hipError_t launch_beam_current(const GridDesc& g, int64_t n_beam, const wk_beam_
         hipLaunchKernelGGL(k_beam_scatter, dim3(nblocks(n_beam, kBlock)), dim3(kBlock), 0, s, g, n_beam, b,
                            fill, order);
     }
-    const size_t lds = sizeof(double) * (g.n_r + 1);
+    if (n_beam > 0)
+        hipLaunchKernelGGL(k_bin_sort, dim3(g.n_xi), dim3(kSortT), 0, s, start, order, sort_tmp);
+    const size_t lds = sizeof(double) * (((g.n_r + 2) & ~1) + 2 * kRowChunk) + sizeof(int) * kRowChunk;
     hipLaunchKernelGGL(k_beam_rows, dim3(g.n_xi), dim3(kBlock), lds, s, g, b, start, order, jb);
     return hipGetLastError();
 }
