@@ -142,6 +142,19 @@ inline double __shfl_xor(double v, int mask, int = 64)
     return r;
 }
 
+template <typename V>
+inline V __shfl_up(V v, unsigned delta, int = 64)
+{
+    static_assert(sizeof(V) <= 8, "shuffled value");
+    int64_t u = 0;
+    memcpy(&u, &v, sizeof(V));
+    const int l = (int)(threadIdx.x & 63);
+    u = wk_model::lane_of(u, l >= (int)delta ? l - (int)delta : l);
+    V r;
+    memcpy(&r, &u, sizeof(V));
+    return r;
+}
+
 // Host launch interface seen by kernel sources (the model calls the device
 // code directly and never launches).
 struct dim3 {

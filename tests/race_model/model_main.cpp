@@ -142,10 +142,8 @@ const Entry kEntries[] = {
     {"f64-cyl-warm-256x4-res", WK_RUN(double, WK_CYL, true, 256, 4, true, false)},
     {"f64-cyl-cold-256x4-res", WK_RUN(double, WK_CYL, false, 256, 4, true, false)},
     {"f64-slab-warm-256x4-res", WK_RUN(double, WK_SLAB, true, 256, 4, true, false)},
-    {"f64-slab-cold-256x4-res", WK_RUN(double, WK_SLAB, false, 256, 4, true, false)},
     {"f64-cyl-warm-256x4-stream", WK_RUN(double, WK_CYL, true, 256, 4, false, false)},
     {"f64-cyl-warm-512x4-res", WK_RUN(double, WK_CYL, true, 512, 4, true, false)},
-    {"f64-cyl-warm-512x16-res", WK_RUN(double, WK_CYL, true, 512, 16, true, false)},
     {"f64-cyl-warm-1024x8-res", WK_RUN(double, WK_CYL, true, 1024, 8, true, false)},
     {"f64-cyl-warm-512x8-big-stream", WK_RUN(double, WK_CYL, true, 512, 8, false, true)},
     {"f32-cyl-warm-512x8-res", WK_RUN(float, WK_CYL, true, 512, 8, true, false)},
