@@ -48,12 +48,16 @@ __device__ __forceinline__ dev::Group member_group(const MarchDesc& full, int ra
     return grp;
 }
 
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS, bool TRAJ = false>
+// SEL: group exchanges re-read only the partials not yet arrived (the batch,
+// whose members take their tickets over time); a single response, whose
+// members start together, reloads every partial on each try.
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG, int WPS, bool TRAJ = false,
+          bool SEL = false>
 __global__ __launch_bounds__(T, WPS) void k_march(MarchLaunch L)
 {
     extern __shared__ double smem[];
     __shared__ int s_ticket;
-    using M = dev::Marcher<R, GEOM, WARM, T, K, RES, BIG>;
+    using M = dev::Marcher<R, GEOM, WARM, T, K, RES, BIG, SEL>;
     for (;;) {
         int inst = 0, rank = blockIdx.x;
         if (L.descs) {
@@ -88,6 +92,11 @@ hipError_t go(const MarchLaunch& L, int grid, size_t lds, hipStream_t s, int* oc
         return hipErrorInvalidValue;
     } else {
         auto kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd>;
+        // batches (not the large-grid or single-workgroup shapes, which a
+        // batch does not use) with selective re-reads
+        if constexpr (!S.big && S.kp <= 8) {
+            if (L.descs) kern = k_march<R, GEOM, WARM, S.threads, S.kp, S.resident, S.big, S.waves_per_simd, false, true>;
+        }
         if (L.one.traj) {
             // particle radii recorded: an FP64 single response only
             if constexpr (sizeof(R) == 8) {

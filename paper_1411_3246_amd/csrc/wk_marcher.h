@@ -350,7 +350,11 @@ struct Acc {
 // The descriptor a Marcher gets is its own workgroup's share of the response:
 // the particle pointers and count are those of its band of cells, the grid
 // and field pointers those of the whole response.
-template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = false>
+// SEL: a group exchange re-reads only the partials that have not yet arrived
+// (the batched and single-response march, whose members often wait for
+// partners that start later); otherwise every try reloads all of them (the
+// pipelined cycle, whose members run in step).
+template <typename R, int GEOM, bool WARM, int T, int K, bool RES, bool BIG = false, bool SEL = false>
 struct Marcher {
     static constexpr bool kBig = BIG;
     static constexpr int kT = T;
@@ -645,25 +649,48 @@ struct Marcher {
         const int G = grp.G;
         const int items = NR * N1;
         const unsigned want = e & 3u;
+        static_assert(B * MAXG <= 32, "arrival bits of a batch fit one word");
         for (int base = tid; base < items; base += B * T) {
             double v[B][MAXG];
+            // bit c * MAXG + h: partial h of item c still to be read (SEL)
+            unsigned missing = 0;
+#pragma unroll
+            for (int c = 0; c < B; ++c)
+#pragma unroll
+                for (int h = 0; h < MAXG; ++h) {
+                    v[c][h] = 0.0;
+                    if (SEL && base + c * T < items && h < G) missing |= 1u << (c * MAXG + h);
+                }
             unsigned long long t0 = 0;
             unsigned tries = 0;
             for (;;) {
-                // every value of the batch, all loads in flight at once
+                // every value of the batch (SEL: every value not yet arrived),
+                // all loads in flight at once
                 bool ok = true;
 #pragma unroll
                 for (int c = 0; c < B; ++c) {
                     const int it = base + c * T;
                     const int q = it / N1, j = it - q * N1;
                     const double* src = slot + (int64_t)q * st + j;
+                    if constexpr (SEL) {
 #pragma unroll
-                    for (int h = 0; h < MAXG; ++h) {
-                        const bool use = it < items && h < G;
-                        v[c][h] = use ? ld_dev(src + h * part) : 0.0;
-                        ok = ok && (!use || tag_of(v[c][h]) == want);
+                        for (int h = 0; h < MAXG; ++h)
+                            if (missing & (1u << (c * MAXG + h))) v[c][h] = ld_dev(src + h * part);
+#pragma unroll
+                        for (int h = 0; h < MAXG; ++h) {
+                            const unsigned bit = 1u << (c * MAXG + h);
+                            if ((missing & bit) && tag_of(v[c][h]) == want) missing &= ~bit;
+                        }
+                    } else {
+#pragma unroll
+                        for (int h = 0; h < MAXG; ++h) {
+                            const bool use = it < items && h < G;
+                            v[c][h] = use ? ld_dev(src + h * part) : 0.0;
+                            ok = ok && (!use || tag_of(v[c][h]) == want);
+                        }
                     }
                 }
+                if constexpr (SEL) ok = missing == 0;
                 if (ok) break;
                 if (++tries > 64) {
                     // a long wait (a partner not yet started, as when a batch
