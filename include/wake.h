@@ -406,7 +406,12 @@ wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
  * wk_gradient_workspace_size bytes (0: the plan or arguments are not
  * supported; the reason is in wk_last_error()) and depends on the plan's
  * workgroup size (wk_plan_set_threads), which the reverse march also uses.
- * The reverse march runs in one workgroup and needs n_r <= 740 (LDS). */
+ * The reverse march needs n_r <= 740 (LDS).  It runs on a group of up to 8
+ * workgroups, each with a share of the particles, that sum their deposited
+ * node adjoints through the workspace: the plan's group
+ * (wk_plan_set_group, capped at 8), else about one particle per thread.
+ * All members must run at once; a member that waits more than 20 s for the
+ * others gives up, and the gradient is then NaN. */
 size_t wk_gradient_workspace_size(const wk_plan* plan, int32_t n_steps, int32_t every);
 wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma, const double* d_plasma_draws,
                               const wk_beam_bufs* beam, const double* d_beam_draws, int32_t n_steps, double dt,

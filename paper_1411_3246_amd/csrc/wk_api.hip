@@ -954,6 +954,7 @@ wk_status wk_gradient_backward(const wk_plan* plan, const wk_plasma_bufs* plasma
     char* ws = (char*)d_workspace;
     wk::GradDesc gd;
     gd.march = make_desc(plan, plasma, nullptr, nullptr, nullptr);
+    gd.march.group = plan->group;   // the reverse march's group (0: chosen from the particle count)
     gd.grid = grid_of(plan);
     gd.beam = *beam;
     gd.n_beam = plan->p.n_beam;

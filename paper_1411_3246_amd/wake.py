@@ -666,12 +666,16 @@ class GradientRun:
     The problem must be FP64 with a two-bunch macroparticle beam."""
 
     def __init__(self, problem: inputs.Problem, n_steps: Optional[int] = None, every: int = 64,
-                 device="cuda", threads: Optional[int] = None):
+                 device="cuda", threads: Optional[int] = None, group: Optional[int] = None):
+        """group: workgroups of the reverse march (None: the library's
+        choice, about two particles per thread and workgroup, at most 8)."""
         import torch
         self.problem = problem
         self.n_steps = problem.n_steps if n_steps is None else int(n_steps)
         self.every = int(every)
         self.plan = Plan(problem, threads)
+        if group is not None:
+            self.plan.set_group(int(group))
         self.device = device
         self.plasma = self.plan.alloc_plasma(device)
         self.beam = self.plan.alloc_beam(device)

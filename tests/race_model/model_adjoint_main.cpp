@@ -155,6 +155,9 @@ int main(int argc, char** argv)
     a.every = every;
     a.np = np;
     a.kp = (int)((np + kT - 1) / kT);
+    // one member (the model runs one workgroup): no exchanges
+    a.group = 1;
+    a.np_m = np;
     a.r_max = in.r_max;
     a.h = in.h;
     a.dxi = in.dxi;
@@ -168,6 +171,10 @@ int main(int argc, char** argv)
     std::vector<double> ybar((size_t)4 * np, 0.0), d0bar(np, 0.0), wbar(np, 0.0);
     a.jbbar = jbbar.data();
     a.scratch = scratch.data();
+    a.member_doubles = ((int64_t)every * 4 + 20) * a.kp * kT;
+    std::vector<unsigned long long> abort_flag(1, 0ull);
+    a.xbuf = nullptr;
+    a.abort = abort_flag.data();
     a.ybar_out = ybar.data();
     a.d0bar_out = d0bar.data();
     a.wbar_out = wbar.data();

@@ -33,9 +33,9 @@ def _case(**kw):
     return inputs.facet_two_bunch(**base)
 
 
-def _gpu(W, p, every=64):
+def _gpu(W, p, every=64, group=None):
     import torch
-    run = W.GradientRun(p, every=every)
+    run = W.GradientRun(p, every=every, group=group)
     g = float(run.forward().item())
     grad = run.backward().cpu().numpy().copy()
     torch.cuda.synchronize()
@@ -84,18 +84,41 @@ def test_objective_matches_oracle(O, W):
     assert c["nonfinite"] == 0 and c["wall"] == 0
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(n_d=1.0, u_th=0.01), dict(geom="slab", r_max=8.0, u_th=0.005),
-                                dict(u_th=0.0, n_r=24, ppc=3)],
-                         ids=["weak-warm", "moderate", "slab", "cold"])
-def test_adjoint_matches_finite_differences(O, W, kw):
+@pytest.mark.parametrize("kw,group", [(dict(), None), (dict(n_d=1.0, u_th=0.01), None),
+                                      (dict(geom="slab", r_max=8.0, u_th=0.005), None),
+                                      (dict(u_th=0.0, n_r=24, ppc=3), None),
+                                      (dict(ppc=16), 3), (dict(geom="slab", r_max=8.0, ppc=16), 8)],
+                         ids=["weak-warm", "moderate", "slab", "cold", "weak-warm-group3", "slab-group8"])
+def test_adjoint_matches_finite_differences(O, W, kw, group):
     p = _case(**kw)
-    print(f"case {kw}", flush=True)
-    _, grad, _ = _gpu(W, p)
+    print(f"case {kw} reverse group {group}", flush=True)
+    _, grad, _ = _gpu(W, p, group=group)
     which = (0, 1, 2, 3, 4) if p.u_th > 0 else (0, 1, 2, 3)
     fd, err = _fd(O, p, which)
     _compare(grad, fd, err, which)
     if p.u_th == 0:
         assert grad[4] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("kw", [dict(), dict(n_r=64, ppc=16, geom="slab", r_max=8.0), dict(u_th=0.0, ppc=7)],
+                         ids=["small", "slab-1024", "cold-ragged"])
+def test_grouped_reverse_matches_one_workgroup(W, kw, prec):
+    """The reverse march split over a group of workgroups (each member a
+    share of the particles, the deposited node adjoints summed over the
+    group four times a slice) against the same march in one workgroup: the
+    sums only change order, so the gradients agree to 1e-9 relative, at
+    group sizes that divide the particles evenly or not, and with members
+    whose last threads hold no particle."""
+    p = _case(**kw).replace(prec=prec)
+    _, ref, _ = _gpu(W, p, group=1)
+    for G in (2, 3, 8):
+        print(f"case {kw} {prec} reverse group {G}", flush=True)
+        _, grad, _ = _gpu(W, p, group=G)
+        which = [i for i in range(5) if ref[i] != 0.0]
+        scale = max(abs(ref[i]) for i in which)
+        for i in range(5):
+            assert abs(grad[i] - ref[i]) <= 1e-9 * abs(ref[i]) + 1e-13 * scale, (G, i, grad[i], ref[i])
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(W):

@@ -219,7 +219,9 @@ def test_adjoint_march_race_free_and_consistent(model, oracle_lib, geom):
     march's adjoints of the initial state (x, y, p_x, p_y), of D0, of w and of
     the beam current satisfy <fbar, dF> = <ybar, dy> against central
     differences of the oracle's march in random directions (1e-6 relative
-    plus 1e-7 absolute, at steps of 1e-6 or 1e-7)."""
+    plus 1e-7 absolute, at steps of 1e-6 or 1e-7).  The model runs the reverse
+    march as one member: the group sum between members is checked on the GPU
+    (tests/test_gpu_gradient.py, grouped against one workgroup)."""
     (_, _, exe, _), d = model
     O = oracle_lib
     kw = dict(geom="slab", r_max=8.0) if geom == "slab" else {}
