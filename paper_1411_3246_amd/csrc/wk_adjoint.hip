@@ -2,12 +2,14 @@
 // response and n beam steps in its frozen fields, with respect to the drive
 // peak density, the common sigma_r, the drive sigma_z, the witness
 // separation and the plasma thermal spread (Section II A model; Eq. (12)
-// beam; thermal loading of the plasma).  FP64 throughout.
+// beam; thermal loading of the plasma).  Node rows, states and adjoints are
+// double; a mixed plan does its per-particle arithmetic in float.
 //
-// Forward (recording): the usual march, which also writes per slice and
-// Heun stage the node rows the derivative needs (psi, psi', E_z, B_theta,
-// J_r, J_z, M1..M5: the "tape") and the particle state every `every` slices
-// (checkpoints); the beam push keeps the state of every step.
+// Forward (recording): the usual march, by the group of workgroups of a
+// plain response, which also writes per slice and Heun stage the node rows
+// the derivative needs (psi, psi', E_z, B_theta, J_r, J_z, M1..M5: the
+// "tape") and the particle state every `every` slices (checkpoints); the
+// beam push keeps the state of every step.
 //
 // Backward: the beam push in reverse (Jacobians of each Boris step by
 // forward-mode dual numbers), which gives the adjoint of the stored fields;
@@ -46,12 +48,16 @@ struct RecordHooks : M::NoRecord {
     double* tape;
     double* ckpt;
     int every;
-    __device__ __forceinline__ RecordHooks(double* t, double* c, int e) : tape(t), ckpt(c), every(e) {}
+    int64_t np, p0;   // particles of the response; this member's first one
+    bool writer;      // the member that writes the tape (the rows are the group's sums)
+    __device__ __forceinline__ RecordHooks(double* t, double* c, int e, int64_t n, int64_t first, bool w)
+        : tape(t), ckpt(c), every(e), np(n), p0(first), writer(w)
+    {
+    }
     __device__ __forceinline__ void before_slice(M& m, int k)
     {
         if (k % every != 0) return;
-        const int64_t np = m.d.np;
-        double* c = ckpt + (int64_t)(k / every) * 4 * np;
+        double* c = ckpt + (int64_t)(k / every) * 4 * np + p0;
         m.for_idx([&](int64_t i, const auto& p) {
             c[i] = p.x;
             c[np + i] = p.y;
@@ -63,6 +69,7 @@ struct RecordHooks : M::NoRecord {
     __device__ __forceinline__ void after_store(M&, int) {}
     __device__ __forceinline__ void before_b(M& m, int k, int stage)
     {
+        if (!writer) return;
         const int N1 = m.N1;
         double* t = tape + ((int64_t)k * 2 + stage) * kTapeRows * N1;
         for (int j = m.tid; j < N1; j += M::kT) {
@@ -80,6 +87,7 @@ struct RecordHooks : M::NoRecord {
     }
     __device__ __forceinline__ void after_b(M& m, int k, int stage, const double* bt)
     {
+        if (!writer) return;
         const int N1 = m.N1;
         double* t = tape + ((int64_t)k * 2 + stage) * kTapeRows * N1;
         for (int j = m.tid; j < N1; j += M::kT) t[TP_B * N1 + j] = bt[j];
@@ -88,13 +96,35 @@ struct RecordHooks : M::NoRecord {
 
 constexpr int kRecK = 8;
 
+// The recording march of one response by a group of full.group workgroups:
+// member `rank` holds the particles of cells [n_r rank / G, n_r (rank + 1) / G)
+// (the split of the plain march); rank 0 stores the fields and the tape.
 template <typename R, int GEOM, bool WARM, int T, bool RES>
-__global__ __launch_bounds__(T) void k_march_record(MarchDesc d, double* tape, double* ckpt, int every)
+__global__ __launch_bounds__(T) void k_march_record(MarchDesc full, double* tape, double* ckpt, int every)
 {
     extern __shared__ double smem[];
     using M = dev::Marcher<R, GEOM, WARM, T, kRecK, RES, false>;
-    M m(d, smem, smem + NUM_ROWS * lds_stride(d.n_r + 1));
-    RecordHooks<M> hooks(tape, ckpt, every);
+    const int rank = blockIdx.x, G = full.group;
+    const int c0 = (int)((int64_t)full.n_r * rank / G);
+    const int c1 = (int)((int64_t)full.n_r * (rank + 1) / G);
+    const int64_t p0 = (int64_t)c0 * full.ppc;
+    MarchDesc d = full;
+    d.p0 = full.p0 + p0;
+    d.np = (int64_t)(c1 - c0) * full.ppc;
+    d.x = full.x + p0;
+    d.px = full.px + p0;
+    d.y = full.y ? full.y + p0 : nullptr;
+    d.py = full.py ? full.py + p0 : nullptr;
+    d.d0 = (const R*)full.d0 + p0;
+    d.w = (const R*)full.w + p0;
+    dev::Group grp;
+    grp.G = G;
+    grp.g = rank;
+    grp.xbuf = full.xbuf;
+    grp.ctr = full.gctr;
+    grp.abort = full.counters + WK_CNT_PIPELINE_ABORT;
+    M m(d, smem, smem + NUM_ROWS * lds_stride(full.n_r + 1), grp, rank == 0, true);
+    RecordHooks<M> hooks(tape, ckpt, every, full.np, p0, rank == 0);
     m.run(hooks);
 }
 
@@ -1073,11 +1103,13 @@ hipError_t launch_record_t(const MarchDesc& d, int threads, double* tape, double
     auto go = [&](auto kern, size_t bytes) -> hipError_t {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(1), dim3(threads), bytes, s, d, tape, ckpt, every);
+        hipLaunchKernelGGL(kern, dim3(d.group), dim3(threads), bytes, s, d, tape, ckpt, every);
         return hipGetLastError();
     };
-    const size_t extra = 2 * (size_t)threads * std::min<int64_t>(kRecK, (d.np + threads - 1) / threads) * sizeof(double);
-    const bool res = d.np <= (int64_t)threads * kRecK && lds + extra <= 159 * 1024;
+    // the largest member's particles
+    const int64_t np = (int64_t)((d.n_r + d.group - 1) / d.group) * d.ppc;
+    const size_t extra = 2 * (size_t)threads * std::min<int64_t>(kRecK, (np + threads - 1) / threads) * sizeof(double);
+    const bool res = np <= (int64_t)threads * kRecK && lds + extra <= 159 * 1024;
     switch (threads) {
     case 256:
         return res ? go(k_march_record<R, GEOM, WARM, 256, true>, lds + extra)

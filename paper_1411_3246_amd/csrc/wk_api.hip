@@ -925,9 +925,19 @@ wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma,
     if (e == hipSuccess)
         e = wk::launch_init_plasma(g, plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec, *plasma, d_plasma_draws, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (load)");
-    const wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
-    e = wk::launch_march_record(md, plan->p.prec, plan->threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt),
-                                every, s);
+    // the recording march by the group of a plain response, its exchange rows
+    // and counter in the plan workspace's march region (zeroed per launch)
+    wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
+    md.group = single_group(plan);
+    char* region = ws + L.plan_ws;
+    md.xbuf = (double*)(region + march_grow_bytes(plan, wk::kMaxGroup));
+    md.gctr = (unsigned*)(region + march_grow_bytes(plan, wk::kMaxGroup) + march_xbuf_bytes(plan->N1, wk::kMaxGroup));
+    if (md.group > 1)
+        e = wk::launch_zero_u32((unsigned*)md.xbuf, (int64_t)march_xbuf_bytes(plan->N1, md.group) / 4, s);
+    if (e == hipSuccess) e = wk::launch_zero_u32(md.gctr, 1, s);
+    if (e == hipSuccess)
+        e = wk::launch_march_record(md, plan->p.prec, plan->threads, (double*)(ws + L.tape), (double*)(ws + L.ckpt),
+                                    every, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (march)");
     e = wk::launch_push_record(g, plan->p.n_beam, *beam, d_fields, plan->p.prec, n_steps, dt,
                                (double*)(ws + L.hist), (unsigned long long*)d_counters, s);

@@ -104,17 +104,21 @@ def test_adjoint_matches_finite_differences(O, W, kw, group):
 @pytest.mark.parametrize("kw", [dict(), dict(n_r=64, ppc=16, geom="slab", r_max=8.0), dict(u_th=0.0, ppc=7)],
                          ids=["small", "slab-1024", "cold-ragged"])
 def test_grouped_reverse_matches_one_workgroup(W, kw, prec):
-    """The reverse march split over a group of workgroups (each member a
-    share of the particles, the deposited node adjoints summed over the
-    group four times a slice) against the same march in one workgroup: the
-    sums only change order, so the gradients agree to 1e-9 relative, at
-    group sizes that divide the particles evenly or not, and with members
-    whose last threads hold no particle."""
+    """The recording forward and the reverse march split over a group of
+    workgroups (each member a share of the particles; the forward's deposits
+    and the reverse's node adjoints summed over the group) against both in
+    one workgroup: the sums only change order, so the objectives agree to
+    1e-10 (FP64) and the gradients to 1e-9 relative, at group sizes that
+    divide the particles evenly or not, and with members whose last threads
+    hold no particle."""
     p = _case(**kw).replace(prec=prec)
-    _, ref, _ = _gpu(W, p, group=1)
+    g_ref, ref, _ = _gpu(W, p, group=1)
     for G in (2, 3, 8):
-        print(f"case {kw} {prec} reverse group {G}", flush=True)
-        _, grad, _ = _gpu(W, p, group=G)
+        print(f"case {kw} {prec} group {G}", flush=True)
+        g, grad, run = _gpu(W, p, group=G)
+        # the recording forward runs on the same group
+        assert g == pytest.approx(g_ref, rel=1e-10 if prec == "fp64" else 1e-6)
+        assert W.counters_dict(run.counters)["pipeline_abort"] == 0
         which = [i for i in range(5) if ref[i] != 0.0]
         scale = max(abs(ref[i]) for i in which)
         for i in range(5):
