@@ -297,7 +297,8 @@ int32_t wk_plan_group(const wk_plan* plan);
  *   2. the caller copies the blob to device memory;
  *   3. wk_batch_response marches every instance in one persistent launch:
  *      each instance by a group of workgroups (enough to hold its particles
- *      in registers and to bring its cost near the per-compute-unit average
+ *      in registers and to bring its cost, weighted by n_r over the batch's
+ *      largest n_r, near the per-compute-unit average
  *      of the batch, at most 16), the workgroups taking tickets (one member
  *      of one instance's group) from a queue in the workspace, longest
  *      instances first.

@@ -508,8 +508,13 @@ namespace {
 
 // Work plan of a batch: instances longest first (by particle-slice updates),
 // each marched by G_i workgroups: enough to hold its particles in registers
-// (8192 per workgroup) and to bring its cost near the per-compute-unit
-// average of the batch, at most kMaxGroup and its number of cells.
+// (8192 per workgroup) and to bring its cost, weighted by n_r / (the batch's
+// largest n_r), near the per-compute-unit average of the batch; at most
+// kMaxGroup and its number of cells.  The weight: every member repeats the
+// grid work of a slice, so an instance with the batch's largest grid has the
+// longest slices and sets the longest chain; one with a smaller grid
+// finishes within the makespan on fewer members and spends less on repeated
+// grid work and exchanges.
 struct BatchSchedule {
     std::vector<int> order;     // instance indices, longest first
     std::vector<int> group;     // G of each instance (original index)
@@ -526,11 +531,15 @@ BatchSchedule batch_schedule(int n, const wk_plan* const* plans)
     B.group.resize(n);
     B.xoff.assign(n, 0);
     double total = 0.0;
-    for (int i = 0; i < n; ++i) total += (double)plans[i]->np * plans[i]->p.n_xi;
+    int nr_max = 1;
+    for (int i = 0; i < n; ++i) {
+        total += (double)plans[i]->np * plans[i]->p.n_xi;
+        nr_max = std::max(nr_max, plans[i]->N);
+    }
     const double per_cu = total / std::max(1, device_cus());
     for (int i = 0; i < n; ++i) {
         const wk_plan* pl = plans[i];
-        const double cost = (double)pl->np * pl->p.n_xi;
+        const double cost = (double)pl->np * pl->p.n_xi * ((double)pl->N / nr_max);
         int G = pl->group > 0 ? pl->group
                               : (int)std::max<double>(std::ceil((double)pl->np / 8192.0), std::ceil(cost / per_cu));
         G = std::max(1, std::min({G, wk::kMaxGroup, pl->N}));

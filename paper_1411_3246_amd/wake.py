@@ -589,9 +589,12 @@ class Scan:
     def set_member_cap(self, cap: int):
         """Re-plan the batch so that no workgroup holds more than `cap`
         particles: instance i gets G_i = max(ceil(n_p / cap), ceil(cost_i /
-        (total cost / compute units))) workgroups, at most 16 and n_r, with
-        cost = n_p n_xi.  cap = 0 restores the library's schedule (the same
-        rule with cap 8192).  Drops a captured graph."""
+        (total / compute units))) workgroups, at most 16 and n_r, with
+        total = sum of n_p n_xi and cost_i = n_p n_xi n_r / (largest n_r):
+        every member repeats the grid work of a slice, so instances with
+        smaller grids are spread over fewer members.  cap = 0 restores the
+        library's schedule (the same rule with cap 8192).  Drops a captured
+        graph."""
         import math
         import torch
         if cap < 0:
@@ -599,11 +602,13 @@ class Scan:
         cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
         total = sum(float(q.n_plasma) * q.n_xi for q in self.problems)
         per_cu = total / max(1, cus)
+        nr_max = max(q.n_r for q in self.problems)
         for q, pl in zip(self.problems, self.plans):
             if cap == 0:
                 pl.set_group(0)
                 continue
-            g = max(math.ceil(q.n_plasma / cap), math.ceil(float(q.n_plasma) * q.n_xi / per_cu))
+            cost = float(q.n_plasma) * q.n_xi * q.n_r / nr_max
+            g = max(math.ceil(q.n_plasma / cap), math.ceil(cost / per_cu))
             pl.set_group(max(1, min(g, 16, q.n_r)))
         ws = max(pl.sizes.workspace for pl in self.plans)
         if ws > self.workspace.numel():

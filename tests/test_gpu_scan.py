@@ -196,3 +196,30 @@ def test_response_tuning_per_class(O, W, tmp_path):
     assert (sim.plan.threads, sim.plan.group) == choice
     for i in range(4):
         assert _rel(_np(sim.fields[i]), ref["fields"][i]) <= 1e-10, i
+
+
+def test_default_schedule_weights_cost_by_grid(W):
+    """The library's batch schedule on the 256-instance scan's plans (mixed
+    n_r): G_i = max(ceil(n_p / 8192), ceil(cost_i / (total / CUs))) with
+    total = sum of n_p n_xi and cost_i = n_p n_xi n_r / (largest n_r),
+    clipped to [1, min(16, n_r)]."""
+    import ctypes as C
+    import math
+    import torch
+    probs = inputs.scan_instances(256)
+    plans = [W.Plan(q) for q in probs]
+    handles = (C.c_void_p * len(plans))(*[p.handle for p in plans])
+    got = [int(W.lib().wk_batch_group(len(plans), handles, i)) for i in range(len(plans))]
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    total = sum(float(q.n_plasma) * q.n_xi for q in probs)
+    nr_max = max(q.n_r for q in probs)
+    want = [max(1, min(16, q.n_r, max(math.ceil(q.n_plasma / 8192),
+                                      math.ceil(float(q.n_plasma) * q.n_xi * q.n_r / nr_max / (total / cus)))))
+            for q in probs]
+    assert got == want
+    # the weight matters here: a smaller grid gets fewer members than its
+    # unweighted cost would give it
+    unweighted = [max(1, min(16, q.n_r, max(math.ceil(q.n_plasma / 8192),
+                                            math.ceil(float(q.n_plasma) * q.n_xi / (total / cus))))) for q in probs]
+    assert sum(got) < sum(unweighted)
+    assert all(g == u for g, u, q in zip(got, unweighted, probs) if q.n_r == nr_max)
