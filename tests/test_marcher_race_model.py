@@ -21,10 +21,18 @@ the oracle's (FP64 within 1e-10 of each field's scale, mixed precision
 ||dE_z|| / ||E_z|| <= 1e-3), which shows that the model executes the march
 faithfully, cross-lane operations included.
 
+The gradient's model also runs both of its marches on groups of 2 and 3
+workgroups, each workgroup a process of its own over one shared mapping of
+device memory: the marcher's exchanges (in the recording march) and the
+reverse march's run as on the device, and their results are held to the
+same bars; a copy with the reverse exchange left out fails them.
+
 What the model does not see: ordering of global memory by the LDS-only
 barrier (on the GPU it orders LDS accesses only; the marcher keeps its
 cross-thread data in LDS except for the large-grid rows, which use the
-waiting barrier) and the exchanges between the workgroups of a group.
+waiting barrier), and races between workgroups, whose exchanges rely on
+tagged values rather than barriers (ThreadSanitizer checks the threads of
+one process).
 """
 import concurrent.futures
 import os
@@ -210,8 +218,8 @@ def test_direct_response_race_free(model, oracle_lib, kw):
     assert int(cnt[0]) == int(c0[0]) and int(cnt[1]) == int(c0[1])
 
 
-@pytest.mark.parametrize("geom", ["cyl", "slab"])
-def test_adjoint_march_race_free_and_consistent(model, oracle_lib, geom):
+@pytest.mark.parametrize("geom,group", [("cyl", 1), ("cyl", 2), ("slab", 3)])
+def test_adjoint_march_race_free_and_consistent(model, oracle_lib, geom, group):
     """The plasma part of the gradient (wk_adjoint.hip): the recording
     forward march, then the reverse march (checkpointed segments of 8 slices)
     seeded by a random adjoint of the stored fields, in the same model: race
@@ -219,9 +227,11 @@ def test_adjoint_march_race_free_and_consistent(model, oracle_lib, geom):
     march's adjoints of the initial state (x, y, p_x, p_y), of D0, of w and of
     the beam current satisfy <fbar, dF> = <ybar, dy> against central
     differences of the oracle's march in random directions (1e-6 relative
-    plus 1e-7 absolute, at steps of 1e-6 or 1e-7).  The model runs the reverse
-    march as one member: the group sum between members is checked on the GPU
-    (tests/test_gpu_gradient.py, grouped against one workgroup)."""
+    plus 1e-7 absolute, at steps of 1e-6 or 1e-7).  With group > 1 both
+    marches run on that many workgroups, each a process of its own over
+    shared device memory: the exchanges between them run as on the device,
+    ThreadSanitizer checks each workgroup's threads, and the results carry
+    the same bars."""
     (_, _, exe, _), d = model
     O = oracle_lib
     kw = dict(geom="slab", r_max=8.0) if geom == "slab" else {}
@@ -233,11 +243,11 @@ def test_adjoint_march_race_free_and_consistent(model, oracle_lib, geom):
     N1, npart = p.n_r + 1, len(st["x"])
     rng = np.random.default_rng(5)
     fbar = rng.standard_normal((4, p.n_xi, N1))
-    fin, ffb, fout = str(d / f"adj-{geom}.in"), str(d / f"adj-{geom}.fbar"), str(d / f"adj-{geom}.out")
+    fin, ffb, fout = str(d / f"adj-{geom}-{group}.in"), str(d / f"adj-{geom}-{group}.fbar"), str(d / f"adj-{geom}-{group}.out")
     _write_input(fin, p, st, jb)
     fbar.tofile(ffb)
-    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0")
-    r = subprocess.run([exe, fin, ffb, fout, "8"], capture_output=True, text=True, timeout=900, env=env)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0 die_after_fork=0")
+    r = subprocess.run([exe, fin, ffb, fout, "8", str(group)], capture_output=True, text=True, timeout=900, env=env)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-6000:]
     assert r.returncode == 0, r.stderr[-2000:]
     out = np.fromfile(fout)
