@@ -21,11 +21,11 @@ the oracle's (FP64 within 1e-10 of each field's scale, mixed precision
 ||dE_z|| / ||E_z|| <= 1e-3), which shows that the model executes the march
 faithfully, cross-lane operations included.
 
-The gradient's model also runs both of its marches on groups of 2 and 3
-workgroups, each workgroup a process of its own over one shared mapping of
-device memory: the marcher's exchanges (in the recording march) and the
-reverse march's run as on the device, and their results are held to the
-same bars; a copy with the reverse exchange left out fails them.
+Some cases run on groups of 2 and 3 workgroups (the plain march, and both
+marches of the gradient), each workgroup a process of its own over one
+shared mapping of device memory: the exchanges between the members run as
+on the device, and the results are held to the same bars; a copy with the
+marcher's or the reverse march's exchange left out fails them.
 
 What the model does not see: ordering of global memory by the LDS-only
 barrier (on the GPU it orders LDS accesses only; the marcher keeps its
@@ -110,6 +110,11 @@ CASES = [
     ("f64-cyl-warm-512x8-big-stream", dict(n_r=40, ppc=16, u_th=0.02)),
     ("f32-cyl-warm-512x8-res", dict(n_r=64, ppc=32, u_th=0.02, prec="mixed")),
     ("f32-cyl-warm-512x8-big-res", dict(n_r=64, ppc=16, u_th=0.02, prec="mixed")),
+    # groups of workgroups (a process per member): exchanges of S and of the
+    # folded moments; a ragged split of 40 cells over 3 members with global
+    # node rows per member
+    ("f64-cyl-warm-256x4-res", dict(n_r=32, ppc=8, u_th=0.02, group=2)),
+    ("f64-cyl-warm-512x8-big-stream", dict(n_r=40, ppc=16, u_th=0.02, group=3)),
 ]
 
 
@@ -125,7 +130,9 @@ def _write_input(path, p, st, jb):
         f.write(np.ascontiguousarray(jb, dtype=np.float64).tobytes())
 
 
-@pytest.mark.parametrize("shape,kw", CASES, ids=[f"{s}-{k['n_r']}x{k['ppc']}" for s, k in CASES])
+@pytest.mark.parametrize("shape,kw", CASES,
+                         ids=[f"{s}-{k['n_r']}x{k['ppc']}" + (f"-group{k['group']}" if "group" in k else "")
+                              for s, k in CASES])
 def test_barrier_schedule_race_free(model, oracle_lib, shape, kw):
     (exe, _, _, _), d = model
     r, p, fout, ref = _run(exe, d, oracle_lib, shape, kw)
@@ -163,6 +170,8 @@ def test_model_reports_a_missing_barrier(tmp_path, oracle_lib):
 
 
 def _run(exe, d, O, shape, kw):
+    kw = dict(kw)
+    group = kw.pop("group", 1)
     base = dict(n_xi=40, n_d=1.0, n_beam=0, prec="fp64")
     base.update(kw)
     full = inputs.facet_two_bunch(**base, name=f"model-{shape}")
@@ -171,11 +180,11 @@ def _run(exe, d, O, shape, kw):
     st = O.load_plasma(p, inputs.plasma_draws(p))
     jb = O.beam_current_analytic(p)
     ref = O.response(p.replace(prec="fp64"), inputs.plasma_draws(p))
-    fin = str(d / f"{shape}-{p.n_r}.in")
-    fout = str(d / f"{shape}-{p.n_r}.out")
+    fin = str(d / f"{shape}-{p.n_r}-{group}.in")
+    fout = str(d / f"{shape}-{p.n_r}-{group}.out")
     _write_input(fin, p, st, jb)
-    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0")
-    r = subprocess.run([exe, fin, fout, shape], capture_output=True, text=True, timeout=600, env=env)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 report_signal_unsafe=0 die_after_fork=0")
+    r = subprocess.run([exe, fin, fout, shape, str(group)], capture_output=True, text=True, timeout=600, env=env)
     return r, p, fout, ref
 
 
