@@ -407,6 +407,9 @@ wk_status wk_ez_peak(const wk_plan* plan, const void* d_fields, double xi_from,
  * wk_gradient_workspace_size bytes (0: the plan or arguments are not
  * supported; the reason is in wk_last_error()) and depends on the plan's
  * workgroup size (wk_plan_set_threads), which the reverse march also uses.
+ * The recording march runs on the group of a plain response
+ * (wk_plan_group) and uses the exchange rows of the plan workspace inside
+ * the gradient workspace.
  * The reverse march needs n_r <= 740 (LDS).  It runs on a group of up to 8
  * workgroups, each with a share of the particles, that sum their deposited
  * node adjoints through the workspace: the plan's group
