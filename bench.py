@@ -280,6 +280,44 @@ def scan_cpu_baseline(probs, n_slices: int):
                       f"time; loading outside the timed marches)"}
 
 
+def push_bench(sim, p):
+    """The standalone beam push (wk_beam_push, Eqs. (8)-(11)): the beam
+    advanced in one response's frozen fields, 1 and n_steps steps per launch,
+    each the best of three runs timed with HIP events (the beam reloaded
+    before each).  Bytes: the state (x, y, xi, px, py, pz, 48 B) is read and
+    written once per launch and stays in registers between steps; each step
+    gathers 3 fields at 4 nodes (12 loads of the field type), which the
+    caches serve (the fields of one response are 34 MB in mixed precision)."""
+    import torch
+    sim.load_beam()
+    sim.beam_current()
+    sim.response()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    nb = p.n_beam
+    field_bytes = 4 if p.prec == "mixed" else 8
+    out = {"workload": p.name, "n_beam": nb, "field_type_bytes": field_bytes, "runs": []}
+    for n in (1, p.n_steps):
+        best = float("inf")
+        for _ in range(3):
+            sim.load_beam()
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            sim.push(n)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        sec = best / 1e3
+        out["runs"].append({
+            "steps_per_launch": n, "ms": best,
+            "particle_steps_per_s": nb * n / sec,
+            "state_GB_per_s": 96.0 * nb / sec / 1e9,
+            "gather_GB_per_s_from_cache": 12.0 * field_bytes * nb * n / sec / 1e9,
+        })
+    return out
+
+
 def grad_bench(args, prec: str = "fp64"):
     """Gradient of the witness gain on the 256 x 2048, 16 ppc, 2e5-particle,
     20-step workload (blowout driver n_d = 8, u_th = 0.02, checkpoints every
@@ -651,6 +689,8 @@ def main():
         "roofline": roofline(updates, kernel_ms, traffic, kernel, launches),
         "diagnostics": {"witness_mean_gain_gamma": gain, "counters": counters},
     }
+    if args.mode == "pipelined":
+        line["beam_push"] = push_bench(sim, p)
     if not args.no_scan:
         sc = scan_bench(args, lambda row: print(f"# tuner {row}", file=sys.stderr, flush=True))
         line["batched_scan"] = sc
