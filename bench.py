@@ -585,14 +585,28 @@ def main():
         conv = convergence_bench(args)
         upd = sum(v["updates"] for v in conv.values())
         ms = sum(v["cycle_ms"] for v in conv.values())
-        print(json.dumps({
+        rec = {
             "metric": "plasma particle-slice updates/s at 1 GPU", "value": upd / (ms * 1e-3),
             "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
             "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
             "config": {"workload": "convergence-2048-cells (cylindrical 2048x16384 + slab 2048x8192)",
                        "ppc": 64, "n_beam": 4_000_000, "beam_steps_timed": args.steps},
-            "convergence": conv}), flush=True)
+            "convergence": conv}
+        if not args.no_cpu:
+            # the FP64 oracle on the first 192 slices of each grid's first
+            # response, extrapolated linearly to a whole response and to the
+            # timed steps (a response of these grids takes minutes on a core)
+            cb = {}
+            for geom, fine in (("cyl", inputs.convergence_cyl()), ("slab", inputs.convergence_slab())):
+                r = cpu_baseline(fine, 192 / fine.n_xi)
+                per_resp = fine.n_plasma * (fine.n_xi - 1) / r["value"]
+                r["extrapolated"] = True
+                r["extrapolated_s_per_response"] = per_resp
+                r["extrapolated_s_for_timed_steps"] = per_resp * args.steps
+                cb[geom] = r
+            rec["cpu_baseline"] = cb
+        print(json.dumps(rec), flush=True)
         return
     if args.workload == "table1-beam":
         tb = table1_beam_bench(args)
