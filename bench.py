@@ -47,7 +47,10 @@ FLOPS_PER_UPDATE = 190.0
 # scaled FETCH_SIZE + WRITE_SIZE counter runs (rocprofv3 --pmc), recorded for
 # a hash of the kernel sources; reported only while the sources match.
 PROFILES = os.path.join(ROOT, "profiles")
-CYCLE_COUNTERS = os.path.join(PROFILES, "k_cycle_two-bunch-512x4096-ppc16-beam1e6.counters.json")
+# one record per launch size: 20 steps (groups of 8 workgroups) and 200
+# steps (one workgroup per response)
+CYCLE_COUNTERS = tuple(os.path.join(PROFILES, f"k_cycle_two-bunch-512x4096-ppc16-beam1e6{s}.counters.json")
+                       for s in ("", "-200steps"))
 SCAN_COUNTERS = os.path.join(PROFILES, "k_march_batch_scan-256.counters.json")
 CONV_COUNTERS = {g: os.path.join(PROFILES, f"k_cycle_convergence-{g}-2048-ppc64.counters.json")
                  for g in ("cyl", "slab")}
@@ -63,19 +66,21 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path: str, updates: float):
+def measured_traffic(paths, updates: float):
     """HBM bytes of a launch of `updates` particle-slice updates from the
-    committed counter record, or None when the kernel sources changed since
-    it was taken, or when the record is of another launch size (another step
-    count changes the cycle's group size and so its exchange traffic)."""
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-    except OSError:
-        return None
-    if source_hash() != rec.get("source_hash") or int(rec.get("updates", -1)) != int(updates):
-        return None
-    return rec["bytes_per_update"] * updates
+    committed counter record of that launch size (one path or several), or
+    None when the kernel sources changed since it was taken, or when no record
+    is of this launch size (another step count changes the cycle's group size
+    and so its exchange traffic)."""
+    for path in ((paths,) if isinstance(paths, str) else paths):
+        try:
+            with open(path) as f:
+                rec = json.load(f)
+        except OSError:
+            continue
+        if source_hash() == rec.get("source_hash") and int(rec.get("updates", -1)) == int(updates):
+            return rec["bytes_per_update"] * updates
+    return None
 
 
 def cpu_model() -> str:

@@ -79,7 +79,7 @@ __device__ __forceinline__ unsigned compact_append(const unsigned* old_order, un
     return total;
 }
 
-template <typename R, class M>
+template <typename R, class M, int K>
 struct CycleHooks : M::NoRecord {
     static constexpr int T = M::kT;
     const CycleDesc& c;
@@ -139,8 +139,9 @@ struct CycleHooks : M::NoRecord {
 
     // Chunks (of T particles) of a bin whose movers are kept in registers
     // until the bin's stayers are counted; the movers of later chunks are
-    // found again.
-    static constexpr int kMvChunks = 4;
+    // found again.  One chunk for the 16-particle shape, whose registers are
+    // already short (one workgroup per response).
+    static constexpr int kMvChunks = K > 8 ? 1 : 4;
 
     // Advance (step n-1) the particles of this subset's old xi bin b, deposit
     // their current, and write the new order.  New bin b is the particles of
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(T, WPS) void k_cycle(CycleDesc c)
             }
             // resident particles are loaded from the template and not stored back
             M m(d, smem, pconst, grp, g == 0, false);
-            CycleHooks<R, M> hooks(c, n, g, wtot, ring, st);
+            CycleHooks<R, M, K> hooks(c, n, g, wtot, ring, st);
             m.run(hooks);
             hooks.finish();
             out_push = hooks.out_push;
