@@ -164,16 +164,18 @@ def test_cycle_bunch_straddles_window_end(O, W, group):
     assert pipe.witness_gain() == pytest.approx(ref["witness_gain"], rel=1e-10)
 
 
-@pytest.mark.parametrize("group", [1, 2])
-def test_cycle_movers_and_dense_bins(O, W, group):
+@pytest.mark.parametrize("group,ppc", [(1, 4), (2, 4), (1, 80)], ids=["group1", "group2", "group1-16-per-thread"])
+def test_cycle_movers_and_dense_bins(O, W, group, ppc):
     """A slow beam (gamma0 = 5, dt = 1: a twelfth of a slice per step) so
     that particles change xi bin in every step, and bins of about 1500
     particles per workgroup at 256 threads (beyond the chunks whose movers
     the bin pass keeps in registers): pipelined cycle against the oracle's
-    sequential cycle, FP64, no bin escapes or order losses."""
+    sequential cycle, FP64, no bin escapes or order losses.  With 80 ppc (5120
+    plasma particles) one workgroup marches 16 particles per thread, the
+    shape that keeps one chunk of movers in registers."""
     import torch
-    base = inputs.facet_two_bunch(n_r=32, n_xi=40, ppc=4, u_th=0.02, n_d=0.5, n_beam=60000, n_steps=4,
-                                  prec="fp64", name="movers")
+    base = inputs.facet_two_bunch(n_r=32 if ppc == 4 else 64, n_xi=40, ppc=ppc, u_th=0.02, n_d=0.5,
+                                  n_beam=60000, n_steps=4, prec="fp64", name="movers")
     p = base.replace(gamma0=5.0, dt=1.0)
     print(f"case {p.name} group={group}", flush=True)
     pipe = W.Simulation(p, threads=256, group=group)
