@@ -934,10 +934,17 @@ wk_status wk_gradient_forward(const wk_plan* plan, const wk_plasma_bufs* plasma,
     if (e == hipSuccess)
         e = wk::launch_init_plasma(g, plan->p.ppc, plan->p.u_th, plan->p.n0, plan->p.prec, *plasma, d_plasma_draws, s);
     if (e != hipSuccess) return hip_status(e, "gradient forward (load)");
-    // the recording march by the group of a plain response, its exchange rows
-    // and counter in the plan workspace's march region (zeroed per launch)
+    // the recording march by a group (the plan's, else the larger of a plain
+    // response's and one workgroup per `threads` particles, at most 8: the
+    // recording march keeps every moment row, so more members pay off
+    // sooner), its exchange rows and counter in the plan workspace's march
+    // region (zeroed per launch)
     wk::MarchDesc md = make_desc(plan, plasma, jb, d_fields, d_counters);
-    md.group = single_group(plan);
+    md.group = plan->group > 0
+                   ? single_group(plan)
+                   : std::max(single_group(plan),
+                              (int)std::min<int64_t>({8, (int64_t)plan->N,
+                                                      (plan->np + plan->threads - 1) / plan->threads}));
     char* region = ws + L.plan_ws;
     md.xbuf = (double*)(region + march_grow_bytes(plan, wk::kMaxGroup));
     md.gctr = (unsigned*)(region + march_grow_bytes(plan, wk::kMaxGroup) + march_xbuf_bytes(plan->N1, wk::kMaxGroup));
