@@ -88,12 +88,16 @@ int default_threads(int64_t np)
     return 1024;
 }
 
-// Workgroups per response of a single march: the plan's choice, else about
-// one per 1024 particles, at most kMaxGroup and the number of cells.
+// Workgroups per response of a single march: the plan's choice, else one
+// for up to 1024 particles and otherwise max(8, n_p / 1024), at most
+// kMaxGroup and the number of cells.  Two or four members are slower than
+// one or eight at 2048-4096 particles: they add the exchanges without
+// shortening a slice enough.
 int single_group(const wk_plan* pl)
 {
-    const int G = pl->group > 0 ? pl->group
-                                : (int)std::min<int64_t>(wk::kMaxGroup, std::max<int64_t>(1, pl->np / 1024));
+    int G = pl->group;
+    if (G <= 0)
+        G = pl->np <= 1024 ? 1 : (int)std::min<int64_t>(wk::kMaxGroup, std::max<int64_t>(8, pl->np / 1024));
     return std::max(1, std::min(G, pl->N));
 }
 
