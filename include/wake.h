@@ -285,7 +285,9 @@ int32_t wk_plan_threads(const wk_plan* plan);
  * on the group beyond the summation order of the deposits.  All workgroups
  * of a group must run at once; the library sizes its launches so that they
  * do, and a wait that exceeds 20 s sets WK_CNT_PIPELINE_ABORT instead of
- * hanging.  wk_plan_group returns the group a single response uses. */
+ * hanging.  wk_plan_group returns the group a single response uses: the
+ * plan's, else 1 up to 1024 macroparticles per slice and max(8, n_p / 1024)
+ * above, at most 16 and n_r. */
 wk_status wk_plan_set_group(wk_plan* plan, int32_t group);
 int32_t wk_plan_group(const wk_plan* plan);
 
